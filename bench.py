@@ -1,0 +1,174 @@
+"""Benchmark of the m-mode Teukolsky Lax-Wendroff engine on one MI355X.
+
+A bench step is one complete forced EMRI evolution of the 6400 x 128 Kerr
+grid (a = 0.9, s = -2, m = 2, circular orbit at r0 = 10M): 40000 iterations of
+the two-step Lax-Wendroff stencil with its compact source passes and the
+waveform extracted at r* = 500M after every iteration, from zero data in HBM.
+value = grid-point updates per second (GPts/s) over the timed steps.
+
+Also reported on the same JSON line:
+  roofline      dominant kernel (the stencil): algorithmic HBM bytes per
+                launch (64 B per point: read and write Phi, Pi) over its
+                average launch duration, from HIP events around every
+                stencil launch of one extra evolution;
+  hbm_grid      the same physics on 12800 x 256 (larger than the last-level
+                cache), GPts/s and algorithmic GB/s;
+  cpu_baseline  the FP64 oracle on the host for a bounded number of
+                iterations of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_POINT = 64.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
+    ap.add_argument("--cpu-iters", type=int, default=16)
+    return ap.parse_args()
+
+
+def make_engine(cfg, nsteps):
+    from paper_1001_3631_amd.engine import Engine
+    g = cfg["grid"]
+    eng = Engine(**g)
+    src = cfg["source"]
+    orbit = eng.orbit_circular(src["r0"], 2 * nsteps + 1, M=g["M"], a=g["a"])
+    eng.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"],
+                   src["cutoff_sigmas"])
+    return eng
+
+
+def run_evolution(eng, zero_phi, zero_pi, nsteps, wave):
+    eng.set_state(zero_phi, zero_pi)
+    eng.step(nsteps, out=wave)
+
+
+def cpu_baseline(cfg, iters):
+    import numpy as np
+    from oracle import teuk_oracle as T
+    g = T.Grid(**cfg["grid"])
+    src = cfg["source"]
+    orbit = T.circular_orbit(g.M, g.a, src["r0"], g.dt, iters)
+    s = T.Source(g, orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"],
+                 src["cutoff_sigmas"])
+    z = np.zeros((g.nth, g.nr), np.complex128)
+    t0 = time.perf_counter()
+    T.evolve(g, z, z, iters, s)
+    dt = time.perf_counter() - t0
+    return {"value": iters * g.nr * g.nth / dt / 1e9, "unit": "GPts/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} iterations of the {cfg['name']} workload (NumPy FP64, one thread), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    import torch
+    from paper_1001_3631_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    cfg = W.KERR_EMRI
+    g = cfg["grid"]
+    n = cfg["steps"]
+    npts = g["nr"] * g["nth"]
+    eng = make_engine(cfg, n)
+    zphi = torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda")
+    zpi = torch.zeros_like(zphi)
+    wave = torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda")
+
+    for _ in range(args.warmup):
+        run_evolution(eng, zphi, zpi, n, wave)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_evolution(eng, zphi, zpi, n, wave)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    eng.check_finite()
+    ms_per_step = elapsed / args.steps * 1e3
+    gpts = args.steps * n * npts / elapsed / 1e9
+    print(f"[bench] {cfg['name']}: {args.steps} evolutions of {n} iterations in {elapsed:.3f} s "
+          f"-> {gpts:.2f} GPts/s", file=sys.stderr, flush=True)
+
+    # dominant kernel: average stencil launch duration from HIP events
+    eng.set_kernel_timing(True)
+    run_evolution(eng, zphi, zpi, n, wave)
+    kms, kn = eng.kernel_timing()
+    eng.set_kernel_timing(False)
+    avg_s = kms / kn * 1e-3
+    achieved = npts * BYTES_PER_POINT / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "lw_step_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
+                "bytes_per_launch": int(npts * BYTES_PER_POINT), "launches_timed": kn}
+    print(f"[bench] stencil launch avg {avg_s*1e6:.2f} us -> {achieved:.0f} GB/s algorithmic",
+          file=sys.stderr, flush=True)
+
+    extra = {}
+    if not args.no_hbm:
+        hc = W.HBM_PLAIN
+        hg = hc["grid"]
+        hn = hc["steps"]
+        heng = make_engine(hc, hn)
+        hphi = torch.zeros((hg["nth"], hg["nr"]), dtype=torch.complex128, device="cuda")
+        hpi = torch.zeros_like(hphi)
+        hwave = torch.empty((hn, hg["nth"]), dtype=torch.complex128, device="cuda")
+        run_evolution(heng, hphi, hpi, hn, hwave)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_evolution(heng, hphi, hpi, hn, hwave)
+        torch.cuda.synchronize()
+        he = time.perf_counter() - t1
+        heng.set_kernel_timing(True)
+        run_evolution(heng, hphi, hpi, hn, hwave)
+        hkms, hkn = heng.kernel_timing()
+        hpts = hg["nr"] * hg["nth"]
+        havg = hkms / hkn * 1e-3
+        extra["hbm_grid"] = {"workload": hc["name"], "iterations": hn,
+                             "gpts": round(hn * hpts / he / 1e9, 3),
+                             "kernel_avg_us": round(havg * 1e6, 2),
+                             "kernel_algorithmic_GBs": round(hpts * BYTES_PER_POINT / havg / 1e9, 1),
+                             "kernel_frac_of_peak": round(hpts * BYTES_PER_POINT / havg / 1e9 / HBM_PEAK_GBS, 4)}
+        print(f"[bench] {hc['name']}: {extra['hbm_grid']}", file=sys.stderr, flush=True)
+        heng.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, args.cpu_iters)
+        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "grid-point updates/s (GPts/s) + % HBM roofline; adjoint/forward time ratio",
+        "value": round(gpts, 4), "unit": "GPts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": [g["nr"], g["nth"]], "iterations": n,
+                   "a": g["a"], "m": g["m"], "s": g["s"], "source": "circular r0=10M",
+                   "extraction": "every iteration at r*=500M", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

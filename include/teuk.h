@@ -1,0 +1,164 @@
+/*
+ * teuk.h - C ABI of the MI355X m-mode Teukolsky Lax-Wendroff engine.
+ *
+ * What it computes (Khanna & McKennon, "Numerical modeling of gravitational
+ * wave sources accelerated by OpenCL"):
+ *   - Sec. 3.1, Eq. (1): the Teukolsky master equation for spin-weight-s
+ *     perturbations of a Kerr black hole (mass M, spin a).
+ *   - Sec. 3.2: tortoise coordinate r*, azimuth phi~, the m-mode ansatz
+ *     Psi = e^{i m phi~} r^3 Phi, the momentum Pi = d_t Phi + b d_r* Phi, the
+ *     first-order system d_t u + D d_r* u = S with u = (Phi, Pi) complex,
+ *     D = diag(b, -b) [d_matrix], and its two-step Lax-Wendroff iteration,
+ *     half step (lw1) then full step (lw2), with second-order centred angular
+ *     differences; boundary conditions Phi = Pi = 0 on both radial ends and,
+ *     at the poles, d_theta Phi = 0 for even |m| or Phi = 0 for odd |m|.
+ *   - The source term T of Eq. (1) is replaced by a Gaussian-smeared point
+ *     particle F (the paper does not print T); F enters the Pi row of S and
+ *     is produced by its own compact data-parallel pass over the cells near
+ *     the orbit, as the paper produces T by its own kernel (Sec. 4).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success or a negative TEUK_E* code; teuk_last_error()
+ *     then holds a message for the calling thread.  No C++ exception crosses
+ *     this boundary.
+ *   - Complex fields are complex128: interleaved (re, im) doubles, laid out
+ *     [theta row j][r* column i], row-major, dense (row pitch = nr).
+ *   - Pointers documented as "device" are HIP device pointers readable and
+ *     writable on the context's stream; "host" pointers are ordinary memory.
+ *     The caller owns every pointer it passes; the library never frees it and
+ *     does not keep it after the call returns (except where stated).
+ *   - Work is enqueued on the stream given to teuk_init_grid and runs
+ *     asynchronously; calls that return host data synchronize that stream.
+ *   - A context is not thread safe; use one context per host thread.
+ *   - The library allocates its own device memory for the state (two time
+ *     levels), the coefficient tables, the orbit and the source windows; it is
+ *     released by teuk_destroy.
+ */
+#ifndef TEUK_H
+#define TEUK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEUK_OK          0
+#define TEUK_EINVAL     -1   /* invalid argument or descriptor            */
+#define TEUK_EDEVICE    -2   /* HIP runtime error (message appended)      */
+#define TEUK_ENONFINITE -3   /* non-finite values found by teuk_check_finite */
+#define TEUK_ENOMEM     -4   /* device or host allocation failed          */
+#define TEUK_ESTATE     -5   /* call order violated (e.g. no source set)  */
+
+typedef struct teuk_ctx teuk_ctx;
+
+/* Grid and physics of one instance.
+ *   M, a      black-hole mass and spin, 0 <= |a| < M                 (Eq. 1)
+ *   s, m      spin weight (-2..2) and azimuthal number              (Eq. 1, ansatz)
+ *   nr, nth   nodes in r* and theta, both ends included: r*_i = rs_min + i h_r,
+ *             h_r = (rs_max - rs_min)/(nr-1); theta_j = j h_th, h_th = pi/(nth-1);
+ *             nr >= 5, nth >= 7
+ *   cfl       dt = cfl * min(h_r, r(rs_min) h_th); 0 < cfl <= 1
+ *   rs_extract extraction radius; the waveform is Phi at the nearest node
+ *   ko_eps    strength of the theta fourth-difference dissipation added in the
+ *             full step (0 = the literal scheme; 0 <= ko_eps <= 1).  The literal
+ *             scheme is weakly unstable for stiff angular modes at the poles. */
+typedef struct {
+    double M, a;
+    int32_t s, m;
+    int32_t nr, nth;
+    double rs_min, rs_max;
+    double cfl;
+    double rs_extract;
+    double ko_eps;
+} teuk_grid_desc;
+
+/* Derived grid quantities (filled by teuk_get_info). */
+typedef struct {
+    double dt, h_r, h_th;
+    double r_plus, r_minus;     /* horizons */
+    int32_t i_ext;              /* extraction column */
+    int32_t nr, nth;
+    int32_t row_pitch;          /* internal row pitch of the state, in complex elements */
+    int64_t steps_done;         /* iterations taken since the last teuk_set_state/teuk_init_pulse */
+} teuk_info;
+
+/* Synthetic point-particle source: F(t, r*, theta) = amplitude
+ *   * G(r* - r*_p(t); sigma_r_cells h_r) * G(theta - theta_p(t); sigma_th_cells h_th)
+ *   * exp(-i m phi~_p(t)),  G(x; s) = exp(-x^2/2s^2)/(sqrt(2 pi) s), zero where
+ *   |x| > cutoff_sigmas * s.  The orbit is sampled at t_k = k dt/2,
+ *   k = 0..nsamples-1: orbit[3k+0] = r*_p, orbit[3k+1] = theta_p,
+ *   orbit[3k+2] = phi~_p (host array, copied at the call).  Iteration n uses
+ *   sample 2n in its half step (lw1, time t_n) and 2n+1 in its full step
+ *   (lw2, time t_n + dt/2); stepping past the last sample is TEUK_ESTATE. */
+typedef struct {
+    double amplitude;
+    double sigma_r_cells, sigma_th_cells, cutoff_sigmas;
+    int64_t nsamples;
+    const double* orbit;
+} teuk_source_desc;
+
+/* Create a context: validate the descriptor, invert r*(r) (Newton on ln(r - r_+)),
+ * build the radial and angular coefficient tables of the first-order system
+ * on the host, copy them to the device and zero the state.  hip_stream is a
+ * hipStream_t (NULL = the null stream).  Synchronizes. */
+int teuk_init_grid(const teuk_grid_desc* desc, void* hip_stream, teuk_ctx** out);
+
+/* Release the context and all library-owned device memory.  NULL is a no-op. */
+int teuk_destroy(teuk_ctx* ctx);
+
+int teuk_get_info(const teuk_ctx* ctx, teuk_info* out);
+
+/* Copy a state in (device, complex128 [nth][nr] each).  The values are taken
+ * as given (no boundary projection).  Resets steps_done and the source clock. */
+int teuk_set_state(teuk_ctx* ctx, const void* phi_dev, const void* pi_dev);
+
+/* Copy the current state out (device, complex128 [nth][nr] each). */
+int teuk_get_state(const teuk_ctx* ctx, void* phi_dev, void* pi_dev);
+
+/* Initial data on the device: Phi = amplitude exp(-(r*-center)^2/(2 width^2)) P(theta),
+ * P = 2^{(|m+s|+|m-s|)/2} sin^{|m+s|}(theta/2) cos^{|m-s|}(theta/2) (the lowest-l
+ * spin-weighted profile), Pi = b d_r* Phi (time-symmetric data), then the
+ * boundary conditions.  Resets steps_done and the source clock. */
+int teuk_init_pulse(teuk_ctx* ctx, double center, double width, double amplitude);
+
+/* Attach (or with NULL detach) the synthetic source.  Copies the orbit. */
+int teuk_set_source(teuk_ctx* ctx, const teuk_source_desc* src);
+
+/* Change the source amplitude without re-uploading the orbit. */
+int teuk_set_amplitude(teuk_ctx* ctx, double amplitude);
+
+/* Fill a host array with a circular equatorial prograde orbit sampled at
+ * t_k = k dt/2, k = 0..nsamples-1: r*_p = r*(r0), theta_p = pi/2,
+ * phi~_p = Omega t_k, Omega = M^{1/2}/(r0^{3/2} + a M^{1/2}).  out has 3*nsamples doubles. */
+int teuk_orbit_circular(double M, double a, double r0, double dt, int64_t nsamples, double* out);
+
+/* Take nsteps iterations (lw1, boundary rows of the half step, lw2 with the
+ * source and dissipation, boundary conditions).  If waveform_dev is not NULL
+ * it receives nsteps*nth complex128: row n is Phi at the extraction column
+ * after iteration n+1 of this call.  Asynchronous. */
+int teuk_step_n(teuk_ctx* ctx, int64_t nsteps, void* waveform_dev);
+
+/* Current Phi column at the extraction radius: nth complex128 (device). */
+int teuk_extract_waveform(const teuk_ctx* ctx, void* out_dev);
+
+/* Synchronize and check that the state is finite; TEUK_ENONFINITE if not. */
+int teuk_check_finite(teuk_ctx* ctx);
+
+/* Measurement aid: while enabled, every stencil launch made by teuk_step_n
+ * is bracketed by a pair of HIP events on the context's stream (the source
+ * pass is not).  teuk_kernel_timing synchronizes and returns the summed
+ * event-to-event time of those launches (ms) and their count since timing
+ * was enabled.  Enabling resets the sums. */
+int teuk_set_kernel_timing(teuk_ctx* ctx, int enable);
+int teuk_kernel_timing(teuk_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* teuk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEUK_H */

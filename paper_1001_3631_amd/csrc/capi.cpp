@@ -1,0 +1,448 @@
+// C ABI of the engine (declared in include/teuk.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/teuk.h"
+#include "geometry.h"
+#include "kernels.h"
+
+using teuk::Geometry;
+using teuk::ThetaRow;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(TEUK_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+constexpr int kSourceBatch = 256;   // iterations of source windows per compact pass
+
+}  // namespace
+
+struct teuk_ctx {
+    Geometry G;
+    hipStream_t stream = nullptr;
+    int ld = 0;
+    double2* plane[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [level][Phi, Pi]
+    int cur = 0;
+    double* d_rnode = nullptr;
+    double* d_rhalf = nullptr;
+    ThetaRow* d_rows = nullptr;
+    int* d_flag = nullptr;
+    double ko_c = 0.0;
+    int nstrips = 0, nseg = 0;
+    int64_t steps_done = 0;
+    // source
+    bool has_src = false;
+    double amplitude = 0.0, sig_r = 0.0, sig_th = 0.0, cut = 0.0;
+    int64_t nsamples = 0;
+    double* d_orbit = nullptr;
+    int win_r = 0, win_t = 0;
+    double2* d_fh = nullptr;
+    double2* d_fn = nullptr;
+    int4* d_org = nullptr;
+    int64_t batch_n0 = -1;
+    int batch_len = 0;
+    // kernel timing (measurement aid)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+namespace {
+
+void free_source(teuk_ctx* c) {
+    (void)hipFree(c->d_orbit);
+    (void)hipFree(c->d_fh);
+    (void)hipFree(c->d_fn);
+    (void)hipFree(c->d_org);
+    c->d_orbit = nullptr;
+    c->d_fh = c->d_fn = nullptr;
+    c->d_org = nullptr;
+    c->has_src = false;
+    c->batch_n0 = -1;
+    c->batch_len = 0;
+}
+
+// Sum the recorded event pairs into the context's totals (synchronizes).
+int flush_timing(teuk_ctx* c) {
+    if (c->ev_used == 0) return TEUK_OK;
+    HIP_TRY(hipEventSynchronize(c->ev_stop[c->ev_used - 1]), "timing sync");
+    for (size_t k = 0; k < c->ev_used; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_start[k], c->ev_stop[k]), "timing elapsed");
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+    }
+    c->ev_used = 0;
+    return TEUK_OK;
+}
+
+void destroy_events(teuk_ctx* c) {
+    for (auto e : c->ev_start) (void)hipEventDestroy(e);
+    for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+    c->ev_start.clear();
+    c->ev_stop.clear();
+    c->ev_used = 0;
+}
+
+constexpr size_t kTimingPool = 2048;
+
+void free_all(teuk_ctx* c) {
+    destroy_events(c);
+    free_source(c);
+    for (auto& lv : c->plane)
+        for (auto& p : lv) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    (void)hipFree(c->d_rnode);
+    (void)hipFree(c->d_rhalf);
+    (void)hipFree(c->d_rows);
+    (void)hipFree(c->d_flag);
+}
+
+int check_ctx(const teuk_ctx* c) {
+    if (c == nullptr) return fail(TEUK_EINVAL, "null context");
+    return TEUK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* teuk_last_error(void) { return g_last_error.c_str(); }
+
+int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
+    if (d == nullptr || out == nullptr) return fail(TEUK_EINVAL, "null descriptor or output");
+    *out = nullptr;
+    if (!(d->ko_eps >= 0.0 && d->ko_eps <= 1.0)) return fail(TEUK_EINVAL, "need 0 <= ko_eps <= 1");
+    teuk_ctx* c = new (std::nothrow) teuk_ctx();
+    if (c == nullptr) return fail(TEUK_ENOMEM, "host allocation failed");
+    std::string err = teuk::build_geometry(d->M, d->a, d->s, d->m, d->nr, d->nth, d->rs_min, d->rs_max,
+                                           d->cfl, d->rs_extract, c->G);
+    if (!err.empty()) {
+        delete c;
+        return fail(TEUK_EINVAL, err);
+    }
+    const Geometry& G = c->G;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ld = (G.nr + 15) / 16 * 16;
+    c->ko_c = d->ko_eps / 16.0;
+    c->nstrips = (G.nr + 61) / 62;
+    c->nseg = (G.nth - 3) / teuk::kStepSeg + 1;
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
+    auto alloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            free_all(c);
+            delete c;
+            return fail(TEUK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        return TEUK_OK;
+    };
+    int rc;
+    for (auto& lv : c->plane)
+        for (auto& p : lv)
+            if ((rc = alloc(reinterpret_cast<void**>(&p), plane_bytes)) != TEUK_OK) return rc;
+    const size_t rbytes = sizeof(double) * teuk::RF_COUNT * static_cast<size_t>(G.nr);
+    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rnode), rbytes)) != TEUK_OK) return rc;
+    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rhalf), rbytes)) != TEUK_OK) return rc;
+    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rows), sizeof(ThetaRow) * G.nth)) != TEUK_OK) return rc;
+    if ((rc = alloc(reinterpret_cast<void**>(&c->d_flag), sizeof(int))) != TEUK_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(c->d_rnode, G.rnode.data(), rbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_rhalf, G.rhalf.data(), rbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_rows, G.rows.data(), sizeof(ThetaRow) * G.nth, hipMemcpyHostToDevice);
+    for (auto& lv : c->plane)
+        for (auto& p : lv)
+            if (e == hipSuccess) e = hipMemset(p, 0, plane_bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return hip_fail(e, "teuk_init_grid");
+    }
+    *out = c;
+    return TEUK_OK;
+}
+
+int teuk_destroy(teuk_ctx* c) {
+    if (c == nullptr) return TEUK_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return TEUK_OK;
+}
+
+int teuk_get_info(const teuk_ctx* c, teuk_info* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (out == nullptr) return fail(TEUK_EINVAL, "null output");
+    out->dt = c->G.dt;
+    out->h_r = c->G.h_r;
+    out->h_th = c->G.h_th;
+    out->r_plus = c->G.r_plus;
+    out->r_minus = c->G.r_minus;
+    out->i_ext = c->G.i_ext;
+    out->nr = c->G.nr;
+    out->nth = c->G.nth;
+    out->row_pitch = c->ld;
+    out->steps_done = c->steps_done;
+    return TEUK_OK;
+}
+
+int teuk_set_state(teuk_ctx* c, const void* phi, const void* pi) {
+    if (int rc = check_ctx(c)) return rc;
+    if (phi == nullptr || pi == nullptr) return fail(TEUK_EINVAL, "null state pointer");
+    const size_t w = sizeof(double2) * c->G.nr;
+    HIP_TRY(hipMemcpy2DAsync(c->plane[c->cur][0], sizeof(double2) * c->ld, phi, w, w, c->G.nth,
+                             hipMemcpyDeviceToDevice, c->stream), "set_state Phi");
+    HIP_TRY(hipMemcpy2DAsync(c->plane[c->cur][1], sizeof(double2) * c->ld, pi, w, w, c->G.nth,
+                             hipMemcpyDeviceToDevice, c->stream), "set_state Pi");
+    c->steps_done = 0;
+    c->batch_n0 = -1;
+    c->batch_len = 0;
+    return TEUK_OK;
+}
+
+int teuk_get_state(const teuk_ctx* c, void* phi, void* pi) {
+    if (int rc = check_ctx(c)) return rc;
+    if (phi == nullptr || pi == nullptr) return fail(TEUK_EINVAL, "null state pointer");
+    const size_t w = sizeof(double2) * c->G.nr;
+    HIP_TRY(hipMemcpy2DAsync(phi, w, c->plane[c->cur][0], sizeof(double2) * c->ld, w, c->G.nth,
+                             hipMemcpyDeviceToDevice, c->stream), "get_state Phi");
+    HIP_TRY(hipMemcpy2DAsync(pi, w, c->plane[c->cur][1], sizeof(double2) * c->ld, w, c->G.nth,
+                             hipMemcpyDeviceToDevice, c->stream), "get_state Pi");
+    return TEUK_OK;
+}
+
+int teuk_init_pulse(teuk_ctx* c, double center, double width, double amplitude) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!(width > 0.0)) return fail(TEUK_EINVAL, "need width > 0");
+    teuk::PulseParams Q;
+    Q.phi = c->plane[c->cur][0];
+    Q.pi = c->plane[c->cur][1];
+    Q.ld = c->ld;
+    Q.nr = c->G.nr;
+    Q.nth = c->G.nth;
+    Q.rpitch = c->G.nr;
+    Q.rnode = c->d_rnode;
+    Q.rnode_rs = c->d_rnode + static_cast<size_t>(teuk::RF_RS) * c->G.nr;
+    Q.rows = c->d_rows;
+    Q.center = center;
+    Q.width = width;
+    Q.amplitude = amplitude;
+    Q.even = (std::abs(c->G.m) % 2 == 0);
+    HIP_TRY(teuk::launch_init_pulse(Q, c->stream), "init_pulse");
+    c->steps_done = 0;
+    c->batch_n0 = -1;
+    c->batch_len = 0;
+    return TEUK_OK;
+}
+
+int teuk_orbit_circular(double M, double a, double r0, double dt, int64_t nsamples, double* out) {
+    if (out == nullptr || nsamples < 0) return fail(TEUK_EINVAL, "bad orbit output");
+    if (!(M > 0.0) || !(std::fabs(a) < M)) return fail(TEUK_EINVAL, "need M > 0 and |a| < M");
+    const double rp = M + std::sqrt(M * M - a * a);
+    if (!(r0 > rp)) return fail(TEUK_EINVAL, "orbit radius inside the horizon");
+    const double rsp = teuk::tortoise_of_x(r0 - rp, M, a);
+    const double Om = std::sqrt(M) / (std::pow(r0, 1.5) + a * std::sqrt(M));
+    for (int64_t k = 0; k < nsamples; ++k) {
+        const double t = static_cast<double>(k) * (0.5 * dt);
+        out[3 * k + 0] = rsp;
+        out[3 * k + 1] = 0.5 * M_PI;
+        out[3 * k + 2] = Om * t;
+    }
+    return TEUK_OK;
+}
+
+int teuk_set_source(teuk_ctx* c, const teuk_source_desc* s) {
+    if (int rc = check_ctx(c)) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream), "set_source sync");
+    free_source(c);
+    if (s == nullptr) return TEUK_OK;
+    if (s->orbit == nullptr || s->nsamples < 2) return fail(TEUK_EINVAL, "orbit needs >= 2 samples");
+    if (!(s->sigma_r_cells > 0.0 && s->sigma_th_cells > 0.0 && s->cutoff_sigmas > 0.0))
+        return fail(TEUK_EINVAL, "source widths and cutoff must be positive");
+    c->amplitude = s->amplitude;
+    c->sig_r = s->sigma_r_cells * c->G.h_r;
+    c->sig_th = s->sigma_th_cells * c->G.h_th;
+    c->cut = s->cutoff_sigmas;
+    c->win_r = static_cast<int>(std::ceil(2.0 * s->cutoff_sigmas * s->sigma_r_cells)) + 2;
+    c->win_t = static_cast<int>(std::ceil(2.0 * s->cutoff_sigmas * s->sigma_th_cells)) + 2;
+    c->nsamples = s->nsamples;
+    const size_t obytes = sizeof(double) * 3 * static_cast<size_t>(s->nsamples);
+    const size_t tbytes = sizeof(double2) * static_cast<size_t>(c->win_r) * c->win_t * kSourceBatch;
+    hipError_t e = hipMalloc(&c->d_orbit, obytes);
+    if (e == hipSuccess) e = hipMalloc(&c->d_fh, tbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->d_fn, tbytes);
+    if (e == hipSuccess) e = hipMalloc(&c->d_org, sizeof(int4) * kSourceBatch);
+    if (e == hipSuccess) e = hipMemcpy(c->d_orbit, s->orbit, obytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_source(c);
+        return hip_fail(e, "set_source");
+    }
+    c->has_src = true;
+    return TEUK_OK;
+}
+
+int teuk_set_amplitude(teuk_ctx* c, double amplitude) {
+    if (int rc = check_ctx(c)) return rc;
+    if (!c->has_src) return fail(TEUK_ESTATE, "no source attached");
+    c->amplitude = amplitude;
+    c->batch_n0 = -1;   // windows must be recomputed
+    c->batch_len = 0;
+    return TEUK_OK;
+}
+
+int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
+    if (int rc = check_ctx(c)) return rc;
+    if (nsteps < 0) return fail(TEUK_EINVAL, "negative step count");
+    if (nsteps == 0) return TEUK_OK;
+    const Geometry& G = c->G;
+    if (c->has_src && 2 * (c->steps_done + nsteps - 1) + 1 >= c->nsamples)
+        return fail(TEUK_ESTATE, "orbit has too few samples for the requested steps");
+    teuk::StepParams P;
+    P.rnode = c->d_rnode;
+    P.rhalf = c->d_rhalf;
+    P.rows = c->d_rows;
+    P.nr = G.nr;
+    P.nth = G.nth;
+    P.ld = c->ld;
+    P.rpitch = G.nr;
+    P.nstrips = c->nstrips;
+    P.nseg = c->nseg;
+    P.dt = G.dt;
+    P.inv_hr = 1.0 / G.h_r;
+    P.ko_c = c->ko_c;
+    P.even = (std::abs(G.m) % 2 == 0);
+    P.i_ext = G.i_ext;
+    P.win_r = c->win_r;
+    P.win_t = c->win_t;
+    double2* wave = static_cast<double2*>(waveform);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = c->steps_done;
+        P.fh = P.fn = nullptr;
+        P.org = nullptr;
+        if (c->has_src) {
+            if (!(n >= c->batch_n0 && n < c->batch_n0 + c->batch_len)) {
+                const int64_t left = nsteps - k;
+                const int nb = static_cast<int>(left < kSourceBatch ? left : kSourceBatch);
+                teuk::SourceParams S;
+                S.n0 = static_cast<int>(n);
+                S.org = c->d_org;
+                S.win_r = c->win_r;
+                S.win_t = c->win_t;
+                S.orbit = c->d_orbit;
+                S.amplitude = c->amplitude;
+                S.sig_r = c->sig_r;
+                S.sig_th = c->sig_th;
+                S.cut = c->cut;
+                S.rs_min = G.rs_min;
+                S.h_r = G.h_r;
+                S.h_th = G.h_th;
+                S.m = G.m;
+                S.nr = G.nr;
+                S.nth = G.nth;
+                S.rnode_rs = c->d_rnode + static_cast<size_t>(teuk::RF_RS) * G.nr;
+                S.rhalf_rs = c->d_rhalf + static_cast<size_t>(teuk::RF_RS) * G.nr;
+                S.rows = c->d_rows;
+                S.fh = c->d_fh;
+                S.fn = c->d_fn;
+                HIP_TRY(teuk::launch_source_pass(S, nb, c->stream), "source pass");
+                c->batch_n0 = n;
+                c->batch_len = nb;
+            }
+            const size_t slot = static_cast<size_t>(n - c->batch_n0);
+            const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
+            P.fh = c->d_fh + slot * wsz;
+            P.fn = c->d_fn + slot * wsz;
+            P.org = c->d_org + slot;
+        }
+        P.phi = c->plane[c->cur][0];
+        P.pi = c->plane[c->cur][1];
+        P.phi_out = c->plane[c->cur ^ 1][0];
+        P.pi_out = c->plane[c->cur ^ 1][1];
+        P.wave = wave ? wave + k * G.nth : nullptr;
+        if (c->timing) {
+            if (c->ev_used == kTimingPool)
+                if (int rc = flush_timing(c)) return rc;
+            while (c->ev_start.size() <= c->ev_used) {
+                hipEvent_t a, b;
+                HIP_TRY(hipEventCreate(&a), "event create");
+                HIP_TRY(hipEventCreate(&b), "event create");
+                c->ev_start.push_back(a);
+                c->ev_stop.push_back(b);
+            }
+            HIP_TRY(hipEventRecord(c->ev_start[c->ev_used], c->stream), "event record");
+        }
+        HIP_TRY(teuk::launch_step(P, c->stream), "step kernel");
+        if (c->timing) {
+            HIP_TRY(hipEventRecord(c->ev_stop[c->ev_used], c->stream), "event record");
+            c->ev_used += 1;
+        }
+        c->cur ^= 1;
+        c->steps_done += 1;
+    }
+    return TEUK_OK;
+}
+
+int teuk_extract_waveform(const teuk_ctx* c, void* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (out == nullptr) return fail(TEUK_EINVAL, "null output");
+    HIP_TRY(hipMemcpy2DAsync(out, sizeof(double2), c->plane[c->cur][0] + c->G.i_ext,
+                             sizeof(double2) * c->ld, sizeof(double2), c->G.nth, hipMemcpyDeviceToDevice,
+                             c->stream), "extract");
+    return TEUK_OK;
+}
+
+int teuk_set_kernel_timing(teuk_ctx* c, int enable) {
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = flush_timing(c)) return rc;
+    c->timing = (enable != 0);
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return TEUK_OK;
+}
+
+int teuk_kernel_timing(teuk_ctx* c, double* total_ms, int64_t* launches) {
+    if (int rc = check_ctx(c)) return rc;
+    if (int rc = flush_timing(c)) return rc;
+    if (total_ms) *total_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    return TEUK_OK;
+}
+
+int teuk_check_finite(teuk_ctx* c) {
+    if (int rc = check_ctx(c)) return rc;
+    HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "finite flag");
+    HIP_TRY(teuk::launch_finite(c->plane[c->cur][0], c->plane[c->cur][1], c->G.nr, c->G.nth, c->ld,
+                                c->d_flag, c->stream), "finite kernel");
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "finite copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "finite sync");
+    if (flag) return fail(TEUK_ENONFINITE, "state holds NaN or Inf");
+    return TEUK_OK;
+}
+
+}  // extern "C"

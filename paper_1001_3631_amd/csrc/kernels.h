@@ -1,0 +1,67 @@
+// Kernel parameter blocks and launchers (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geometry.h"
+
+namespace teuk {
+
+// Rows of theta per wave segment in the streaming stencil.
+constexpr int kStepSeg = 16;
+
+struct StepParams {
+    const double2* phi;         // u^n planes [nth][ld]
+    const double2* pi;
+    double2* phi_out;           // u^{n+1} planes
+    double2* pi_out;
+    const double* rnode;        // radial records, field-major with pitch rpitch
+    const double* rhalf;
+    const ThetaRow* rows;       // nth angular records
+    int nr, nth, ld, rpitch;
+    int nstrips, nseg;          // work decomposition: strips of 62 columns x theta segments
+    double dt, inv_hr, ko_c;    // ko_c = ko_eps / 16
+    int even;                   // |m| even: Neumann poles, else Dirichlet
+    int i_ext;
+    double2* wave;              // nth entries for this iteration, or null
+    // source windows of this iteration (null when no source)
+    const double2* fh;          // half points: [win_t][win_r]
+    const double2* fn;          // nodes: [win_t][win_r]
+    const int4* org;            // window origins: half (col0,row0), node (col0,row0)
+    int win_r, win_t;
+};
+
+struct SourceParams {
+    int n0;                     // first iteration (source clock) of the batch
+    int4* org;                  // out, per iteration: half (col0,row0), node (col0,row0)
+    int win_r, win_t;
+    const double* orbit;        // device copy of the orbit samples (3 per sample)
+    double amplitude, sig_r, sig_th, cut;
+    double rs_min, h_r, h_th;   // grid origin and spacings (window placement)
+    int m, nr, nth;
+    const double* rnode_rs;     // r* of nodes
+    const double* rhalf_rs;     // r* of half points
+    const ThetaRow* rows;
+    double2* fh;                // output tables, batch-major
+    double2* fn;
+};
+
+struct PulseParams {
+    double2* phi;
+    double2* pi;
+    int ld, nr, nth, rpitch;
+    const double* rnode;
+    const double* rnode_rs;
+    const ThetaRow* rows;
+    double center, width, amplitude;
+    int even;
+};
+
+int step_segment_rows();
+hipError_t launch_step(const StepParams& P, hipStream_t stream);
+hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream);
+hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream);
+hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,
+                         hipStream_t stream);
+
+}  // namespace teuk

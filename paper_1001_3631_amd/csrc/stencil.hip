@@ -1,0 +1,316 @@
+// Device kernels of the engine: the single-step streaming stencil, the
+// compact source pass, initial data, and small utilities.
+//
+// Layout in HBM: Phi and Pi are two planes of double2 (complex, interleaved)
+// [nth][ld], r* contiguous, ld = nr rounded up to 16 elements (256-byte rows).
+// Coefficients are never stored as 2D fields: each wave keeps the radial
+// records of its 64 columns in registers and forms b, w, c_t, m_r, C_0 per
+// point from them and one angular record per row (see geometry.h).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "lw_point.h"
+
+namespace teuk {
+
+namespace {
+
+__device__ __forceinline__ double2 shfl_dn1(double2 v) {
+    return make_double2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
+}
+__device__ __forceinline__ double2 shfl_up1(double2 v) {
+    return make_double2(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
+}
+
+__device__ __forceinline__ double2 src_lookup(const double2* __restrict__ tab, int c0, int r0,
+                                              int win_r, int win_t, int col, int row) {
+    if (tab == nullptr) return make_double2(0.0, 0.0);
+    const unsigned dc = static_cast<unsigned>(col - c0);
+    const unsigned dr = static_cast<unsigned>(row - r0);
+    if (dc < static_cast<unsigned>(win_r) && dr < static_cast<unsigned>(win_t))
+        return tab[dr * win_r + dc];
+    return make_double2(0.0, 0.0);
+}
+
+// Workgroups are handed to the 8 XCDs round robin; renumber them so that each
+// XCD walks a contiguous range of work items (vertically adjacent segments of
+// the same column strip share halo rows in that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+    const int per = nwg / 8;
+    const int full = per * 8;
+    if (b >= full) return b;
+    return (b % 8) * per + (b / 8);
+}
+
+}  // namespace
+
+// One Lax-Wendroff iteration.  Each wave owns a strip of 64 columns (62
+// written, one halo column on each side) and a segment of theta rows, and
+// streams down the rows: load row jj of u^n, form the half-step row jj-1,
+// then the full-step row jj-2.  Radial neighbours come from the adjacent
+// lane; the theta window lives in registers (the loop is fully unrolled).
+template <int SEG>
+__global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
+    const int lane = threadIdx.x & 63;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = wg * 4 + (threadIdx.x >> 6);
+    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
+    const int strip = item / P.nseg;
+    const int seg = item - strip * P.nseg;
+    const int i = strip * 62 - 1 + lane;
+    const bool in_col = (i >= 0) && (i < P.nr);
+    const bool writer = in_col && lane >= 1 && lane <= 62;
+    const bool interior_col = (i >= 1) && (i <= P.nr - 2);
+    const int jlo = seg * SEG;
+    const int jhi = (seg == P.nseg - 1) ? P.nth : jlo + SEG;
+    const int nth = P.nth;
+    const int ld = P.ld;
+
+    int4 org = make_int4(0, 0, 0, 0);
+    if (P.org != nullptr) org = *P.org;
+    const int ic = min(max(i, 0), P.nr - 1);
+    const int ih = min(max(i, 0), P.nr - 2);
+    const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+    const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+
+    const double2 z = make_double2(0.0, 0.0);
+    double2 uP[SEG + 6], uQ[SEG + 6];     // u^n, own column, rows jlo-2+t
+    double2 sP[SEG + 6], sQ[SEG + 6], dP[SEG + 6], dQ[SEG + 6];
+    double2 hP[SEG + 6], hQ[SEG + 6];     // half-step values at i+1/2, rows jlo-2+t
+    double2 gP[SEG + 6], gQ[SEG + 6];     // half-step values at i-1/2 (from lane-1)
+    double2 oP1 = z, oQ1 = z;             // full-step row 1 (for the pole row 0)
+    double2 oPp = z, oQp = z;             // previous full-step row (for the last pole row)
+
+#pragma unroll
+    for (int t = 0; t < SEG + 6; ++t) {
+        const int jj = jlo - 2 + t;
+        if (jj <= jhi + 1) {
+            // ---- load row jj of u^n and form column sums/differences ----
+            double2 p = z, q = z;
+            if (jj >= 0 && jj < nth && in_col) {
+                p = P.phi[static_cast<size_t>(jj) * ld + i];
+                q = P.pi[static_cast<size_t>(jj) * ld + i];
+            }
+            uP[t] = p;
+            uQ[t] = q;
+            const double2 pN = shfl_dn1(p), qN = shfl_dn1(q);
+            sP[t] = c_add(p, pN);
+            sQ[t] = c_add(q, qN);
+            dP[t] = c_sub(pN, p);
+            dQ[t] = c_sub(qN, q);
+
+            // ---- half step (lw1) at (i+1/2, jh), jh = jj - 1 ----
+            if (t >= 2) {
+                const int jh = jj - 1;
+                hP[t - 1] = z;
+                hQ[t - 1] = z;
+                if (jh >= 1 && jh <= nth - 2) {
+                    const ThetaRow R = P.rows[jh];
+                    const Coef c = coef_at(rh, R.cos_th, R.sin2);
+                    const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
+                    lw_point(c, R.alpha, R.beta, R.gamma, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
+                             dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
+                             c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
+                } else if (jh == nth - 1 && t >= 4) {
+                    hP[t - 1] = pole_value(P.even, hP[t - 2], hP[t - 3]);
+                    hQ[t - 1] = pole_value(P.even, hQ[t - 2], hQ[t - 3]);
+                }
+                if (jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
+                    hP[t - 3] = pole_value(P.even, hP[t - 2], hP[t - 1]);
+                    hQ[t - 3] = pole_value(P.even, hQ[t - 2], hQ[t - 1]);
+                    gP[t - 3] = shfl_up1(hP[t - 3]);
+                    gQ[t - 3] = shfl_up1(hQ[t - 3]);
+                }
+                gP[t - 1] = shfl_up1(hP[t - 1]);
+                gQ[t - 1] = shfl_up1(hQ[t - 1]);
+            }
+
+            // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
+            if (t >= 4) {
+                const int jf = jj - 2;
+                if (jf >= jlo && jf < jhi) {
+                    double2 oP = z, oQ = z;
+                    const bool pole = (jf == 0) || (jf == nth - 1);
+                    if (!pole && interior_col) {
+                        const ThetaRow R = P.rows[jf];
+                        const Coef c = coef_at(rn, R.cos_th, R.sin2);
+                        const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
+                        // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
+                        const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
+                        const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
+                        const double2 sPp = c_add(hP[t - 1], gP[t - 1]);
+                        const double2 sQ0 = c_add(hQ[t - 2], gQ[t - 2]);
+                        const double2 dP0 = c_sub(hP[t - 2], gP[t - 2]);
+                        const double2 dQ0 = c_sub(hQ[t - 2], gQ[t - 2]);
+                        lw_point(c, R.alpha, R.beta, R.gamma, sPm, sP0, sPp, sQ0, dP0, dQ0, F,
+                                 P.dt, P.inv_hr, uP[t - 2], uQ[t - 2], oP, oQ);
+                        if (P.ko_c != 0.0) {
+                            const double sg = P.even ? 1.0 : -1.0;
+                            // rows jf-2 .. jf+2; ghost rows -1 and nth reflect row 1 / nth-2
+                            const double2 pm2 = (jf == 1) ? c_scale(sg, uP[t - 2]) : uP[t - 4];
+                            const double2 qm2 = (jf == 1) ? c_scale(sg, uQ[t - 2]) : uQ[t - 4];
+                            const double2 pp2 = (jf == nth - 2) ? c_scale(sg, uP[t - 2]) : uP[t];
+                            const double2 qp2 = (jf == nth - 2) ? c_scale(sg, uQ[t - 2]) : uQ[t];
+                            oP = ko_apply(oP, P.ko_c, pm2, uP[t - 3], uP[t - 2], uP[t - 1], pp2);
+                            oQ = ko_apply(oQ, P.ko_c, qm2, uQ[t - 3], uQ[t - 2], uQ[t - 1], qp2);
+                        }
+                    }
+                    if (!pole) {
+                        if (writer) {
+                            P.phi_out[static_cast<size_t>(jf) * ld + i] = oP;
+                            P.pi_out[static_cast<size_t>(jf) * ld + i] = oQ;
+                            if (P.wave != nullptr && i == P.i_ext) P.wave[jf] = oP;
+                        }
+                        if (jf == 1) { oP1 = oP; oQ1 = oQ; }
+                        if (jf == 2) {   // pole row 0 from rows 1, 2
+                            const double2 p0 = pole_value(P.even, oP1, oP);
+                            const double2 q0 = pole_value(P.even, oQ1, oQ);
+                            if (writer) {
+                                P.phi_out[i] = interior_col ? p0 : z;
+                                P.pi_out[i] = interior_col ? q0 : z;
+                                if (P.wave != nullptr && i == P.i_ext) P.wave[0] = interior_col ? p0 : z;
+                            }
+                        }
+                        if (jf == nth - 2) {   // last pole row from rows nth-2, nth-3
+                            const double2 pl = pole_value(P.even, oP, oPp);
+                            const double2 ql = pole_value(P.even, oQ, oQp);
+                            if (writer) {
+                                P.phi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? pl : z;
+                                P.pi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? ql : z;
+                                if (P.wave != nullptr && i == P.i_ext) P.wave[nth - 1] = interior_col ? pl : z;
+                            }
+                        }
+                        oPp = oP;
+                        oQp = oQ;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Compact source pass: F on the windows near the particle for a batch of
+// iterations.  Block y = iteration in the batch; threads cover the window.
+// Half-point window (time t_n, sample 2n) and node window (t_n + dt/2,
+// sample 2n+1).
+__global__ void __launch_bounds__(256) source_pass_kernel(SourceParams S) {
+    const int b = blockIdx.y;
+    const int n = S.n0 + b;
+    // window origins: first index whose coordinate can lie within cut*sigma
+    const double* sh = S.orbit + 3 * static_cast<size_t>(2 * n);
+    const double* sn_ = S.orbit + 3 * static_cast<size_t>(2 * n + 1);
+    const double Rr = S.cut * S.sig_r, Rt = S.cut * S.sig_th;
+    int4 org;
+    org.x = static_cast<int>(floor((sh[0] - Rr - (S.rs_min + 0.5 * S.h_r)) / S.h_r));
+    org.y = static_cast<int>(floor((sh[1] - Rt) / S.h_th));
+    org.z = static_cast<int>(floor((sn_[0] - Rr - S.rs_min) / S.h_r));
+    org.w = static_cast<int>(floor((sn_[1] - Rt) / S.h_th));
+    if (threadIdx.x == 0 && blockIdx.x == 0) S.org[b] = org;
+    const int npts = S.win_r * S.win_t;
+    for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < 2 * npts; e += blockDim.x * gridDim.x) {
+        const bool node = e >= npts;
+        const int k = node ? e - npts : e;
+        const int dr = k / S.win_r;
+        const int dc = k - dr * S.win_r;
+        const int col = (node ? org.z : org.x) + dc;
+        const int row = (node ? org.w : org.y) + dr;
+        const double* smp = S.orbit + 3 * static_cast<size_t>(2 * n + (node ? 1 : 0));
+        double2 F = make_double2(0.0, 0.0);
+        const int ncol = node ? S.nr : S.nr - 1;
+        if (col >= 0 && col < ncol && row >= 0 && row < S.nth) {
+            const double rs = (node ? S.rnode_rs : S.rhalf_rs)[col];
+            const double th = S.rows[row].theta;
+            const double gr = gauss_cut(rs - smp[0], S.sig_r, S.cut);
+            const double gt = gauss_cut(th - smp[1], S.sig_th, S.cut);
+            const double amp = S.amplitude * gr * gt;
+            double sn, cs;
+            sincos(S.m * smp[2], &sn, &cs);
+            F = make_double2(amp * cs, -amp * sn);
+        }
+        double2* out = (node ? S.fn : S.fh) + static_cast<size_t>(b) * npts;
+        out[k] = F;
+    }
+}
+
+// Initial data: Gaussian in r* times the angular profile, Pi = b d_r* Phi,
+// then the boundary conditions (pole rows recomputed from rows 1, 2).
+__global__ void __launch_bounds__(256) init_pulse_kernel(PulseParams Q) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= Q.nr) return;
+    const RCol rn = load_rcol(Q.rnode, Q.rpitch, i);
+    const double rs = Q.rnode_rs[i];
+    const double x = rs - Q.center;
+    const double rad = Q.amplitude * exp(-x * x / (2.0 * Q.width * Q.width));
+    auto value = [&](int jr, double2& p, double2& q) {
+        const ThetaRow R = Q.rows[jr];
+        const Coef c = coef_at(rn, R.cos_th, R.sin2);
+        const double phi = rad * R.prof;
+        p = make_double2(phi, 0.0);
+        q = make_double2(-c.b * x / (Q.width * Q.width) * phi, 0.0);
+    };
+    double2 p = make_double2(0.0, 0.0), q = p;
+    if (i > 0 && i < Q.nr - 1) {
+        if (j == 0 || j == Q.nth - 1) {
+            if (Q.even) {
+                double2 p1, q1, p2, q2;
+                const int j1 = (j == 0) ? 1 : Q.nth - 2;
+                const int j2 = (j == 0) ? 2 : Q.nth - 3;
+                value(j1, p1, q1);
+                value(j2, p2, q2);
+                p = pole_value(true, p1, p2);
+                q = pole_value(true, q1, q2);
+            }
+        } else {
+            value(j, p, q);
+        }
+    }
+    Q.phi[static_cast<size_t>(j) * Q.ld + i] = p;
+    Q.pi[static_cast<size_t>(j) * Q.ld + i] = q;
+}
+
+// Finiteness check of a plane pair; sets *flag to 1 on any NaN/Inf.
+__global__ void __launch_bounds__(256) finite_kernel(const double2* __restrict__ a,
+                                                     const double2* __restrict__ b, int nr, int nth,
+                                                     int ld, int* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nr) return;
+    const double2 u = a[static_cast<size_t>(j) * ld + i];
+    const double2 v = b[static_cast<size_t>(j) * ld + i];
+    if (!isfinite(u.x) || !isfinite(u.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+
+int step_segment_rows() { return kStepSeg; }
+
+hipError_t launch_step(const StepParams& P, hipStream_t stream) {
+    const int items = P.nstrips * P.nseg;
+    const int blocks = (items + 3) / 4;
+    hipLaunchKernelGGL(lw_step_kernel<kStepSeg>, dim3(blocks), dim3(256), 0, stream, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream) {
+    const int npts = 2 * S.win_r * S.win_t;
+    const int bx = (npts + 255) / 256;
+    hipLaunchKernelGGL(source_pass_kernel, dim3(bx, nbatch), dim3(256), 0, stream, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream) {
+    hipLaunchKernelGGL(init_pulse_kernel, dim3((Q.nr + 255) / 256, Q.nth), dim3(256), 0, stream, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(finite_kernel, dim3((nr + 255) / 256, nth), dim3(256), 0, stream, a, b, nr, nth,
+                       ld, flag);
+    return hipGetLastError();
+}
+
+}  // namespace teuk

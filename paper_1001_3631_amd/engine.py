@@ -1,0 +1,148 @@
+"""Python face of the engine: one Engine per (instance, stream).
+
+Thin marshalling over the C ABI (include/teuk.h).  PyTorch only provides
+device memory and the stream; every step of the evolution runs in the HIP
+library.  Complex fields are torch.complex128 tensors of shape (nth, nr) on
+the current HIP device.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_device(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128):
+        raise TypeError(f"{name} must be a complex128 tensor on the HIP device")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
+
+
+class Engine:
+    """One evolving instance.
+
+    Parameters follow teuk_grid_desc: M, a, s, m, nr, nth, rs_min, rs_max,
+    cfl, rs_extract, ko_eps.
+    """
+
+    def __init__(self, M, a, s, m, nr, nth, rs_min, rs_max, cfl=0.5, rs_extract=None,
+                 ko_eps=0.5, stream=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the engine needs a HIP device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        desc = L.GridDesc(float(M), float(a), int(s), int(m), int(nr), int(nth), float(rs_min),
+                          float(rs_max), float(cfl),
+                          float(rs_max if rs_extract is None else rs_extract), float(ko_eps))
+        ctx = ctypes.c_void_p()
+        L.check(self._lib.teuk_init_grid(ctypes.byref(desc), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.m = int(m)
+        self._orbit = None
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self._lib.teuk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries ------------------------------------------------------------
+    @property
+    def info(self):
+        inf = L.Info()
+        L.check(self._lib.teuk_get_info(self.ctx, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in L.Info._fields_}
+
+    @property
+    def shape(self):
+        i = self.info
+        return (i["nth"], i["nr"])
+
+    # -- state --------------------------------------------------------------
+    def set_state(self, phi, pi):
+        _need_device(phi, self.shape, "phi")
+        _need_device(pi, self.shape, "pi")
+        L.check(self._lib.teuk_set_state(self.ctx, _ptr(phi), _ptr(pi)))
+
+    def get_state(self):
+        nth, nr = self.shape
+        phi = torch.empty((nth, nr), dtype=torch.complex128, device="cuda")
+        pi = torch.empty_like(phi)
+        L.check(self._lib.teuk_get_state(self.ctx, _ptr(phi), _ptr(pi)))
+        return phi, pi
+
+    def init_pulse(self, center, width, amplitude=1.0):
+        L.check(self._lib.teuk_init_pulse(self.ctx, float(center), float(width), float(amplitude)))
+
+    # -- source -------------------------------------------------------------
+    def orbit_circular(self, r0, nsamples, M=1.0, a=None):
+        """Orbit samples (nsamples, 3) from the library's own orbit builder."""
+        info = self.info
+        if a is None:
+            raise ValueError("pass the spin a of this instance")
+        out = np.zeros((int(nsamples), 3), dtype=np.float64)
+        L.check(self._lib.teuk_orbit_circular(float(M), float(a), float(r0), float(info["dt"]),
+                                              int(nsamples),
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_source(self, orbit, amplitude=1.0, sigma_r_cells=2.0, sigma_th_cells=2.0,
+                   cutoff_sigmas=8.0):
+        if orbit is None:
+            L.check(self._lib.teuk_set_source(self.ctx, None))
+            self._orbit = None
+            return
+        orbit = np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3)
+        self._orbit = orbit
+        desc = L.SourceDesc(float(amplitude), float(sigma_r_cells), float(sigma_th_cells),
+                            float(cutoff_sigmas), orbit.shape[0],
+                            orbit.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        L.check(self._lib.teuk_set_source(self.ctx, ctypes.byref(desc)))
+
+    def set_amplitude(self, amplitude):
+        L.check(self._lib.teuk_set_amplitude(self.ctx, float(amplitude)))
+
+    # -- evolution ----------------------------------------------------------
+    def step(self, nsteps, waveform=True, out=None):
+        """Take nsteps iterations; returns the (nsteps, nth) waveform or None."""
+        nth = self.shape[0]
+        w = None
+        if waveform:
+            w = out if out is not None else torch.empty((int(nsteps), nth), dtype=torch.complex128,
+                                                        device="cuda")
+            _need_device(w, (int(nsteps), nth), "waveform")
+        L.check(self._lib.teuk_step_n(self.ctx, int(nsteps), _ptr(w) if w is not None else None))
+        return w
+
+    def extract(self):
+        nth = self.shape[0]
+        w = torch.empty((nth,), dtype=torch.complex128, device="cuda")
+        L.check(self._lib.teuk_extract_waveform(self.ctx, _ptr(w)))
+        return w
+
+    def set_kernel_timing(self, enable):
+        L.check(self._lib.teuk_set_kernel_timing(self.ctx, 1 if enable else 0))
+
+    def kernel_timing(self):
+        """(summed stencil-launch time in ms, number of timed launches)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        L.check(self._lib.teuk_kernel_timing(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def check_finite(self):
+        L.check(self._lib.teuk_check_finite(self.ctx))

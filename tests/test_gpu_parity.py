@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: relative L2 <= 1e-12 over (Phi, Pi) and the waveform after the full run;
+single iterations on random states <= 1e-13.  Sizes span several column
+strips (62 columns each) and theta segments (16 rows) with ragged tails.
+The oracle never sees a GPU value except where a test deliberately hands the
+GPU state to one oracle iteration (full-size check).
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import teuk_oracle as T
+from paper_1001_3631_amd import workloads as W
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1001_3631_amd import _lib
+    _lib.load()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2)) / max(np.sqrt(np.sum(np.abs(b) ** 2)), 1e-300))
+
+
+def gpu_engine(grid):
+    from paper_1001_3631_amd.engine import Engine
+    return Engine(**grid)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_source(eng, grid, src, nsteps):
+    orbit = eng.orbit_circular(src["r0"], 2 * nsteps + 1, M=grid["M"], a=grid["a"])
+    eng.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+
+
+def oracle_source(g, src, nsteps):
+    orbit = T.circular_orbit(g.M, g.a, src["r0"], g.dt, nsteps)
+    return T.Source(g, orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+
+
+SRC = dict(r0=10.0, amplitude=1.0, sigma_r_cells=2.0, sigma_th_cells=2.0, cutoff_sigmas=8.0)
+
+
+@pytest.mark.parametrize("grid", [
+    W.SCHWARZSCHILD_PULSE["grid"],
+    dict(M=1.0, a=0.9, s=-2, m=2, nr=300, nth=41, rs_min=-50.0, rs_max=100.0, cfl=0.5, rs_extract=30.0, ko_eps=0.5),
+    dict(M=1.0, a=0.5, s=-2, m=3, nr=131, nth=23, rs_min=-30.0, rs_max=70.0, cfl=0.5, rs_extract=30.0, ko_eps=0.5),
+])
+def test_initial_pulse_parity(grid):
+    eng = gpu_engine(grid)
+    eng.init_pulse(50.0 if grid["rs_max"] > 200 else 20.0, 4.0, 1.0)
+    p, q = eng.get_state()
+    g = T.Grid(**grid)
+    rp, rq = T.initial_pulse(g, 50.0 if grid["rs_max"] > 200 else 20.0, 4.0, 1.0)
+    assert rel(host(p), rp) <= 1e-14
+    assert rel(host(q), rq) <= 1e-14
+
+
+STEP_GRIDS = [
+    dict(M=1.0, a=0.6, s=-2, m=2, nr=200, nth=41, rs_min=-20.0, rs_max=40.0, cfl=0.5, rs_extract=10.0, ko_eps=0.5),
+    dict(M=1.0, a=0.9, s=-2, m=1, nr=131, nth=7, rs_min=-20.0, rs_max=40.0, cfl=0.5, rs_extract=10.0, ko_eps=0.5),
+    dict(M=1.0, a=0.0, s=-2, m=3, nr=63, nth=50, rs_min=-20.0, rs_max=40.0, cfl=0.5, rs_extract=10.0, ko_eps=0.0),
+    dict(M=1.0, a=0.99, s=-2, m=4, nr=5, nth=35, rs_min=-20.0, rs_max=40.0, cfl=0.25, rs_extract=10.0, ko_eps=0.5),
+    dict(M=1.0, a=0.3, s=2, m=-2, nr=125, nth=18, rs_min=-20.0, rs_max=40.0, cfl=0.5, rs_extract=10.0, ko_eps=0.3),
+]
+
+
+@pytest.mark.parametrize("grid", STEP_GRIDS)
+@pytest.mark.parametrize("with_source", [False, True])
+def test_single_step_random_state(grid, with_source):
+    g = T.Grid(**grid)
+    phi, pi = W.random_state(g.nth, g.nr, seed=7)
+    eng = gpu_engine(grid)
+    eng.set_state(to_dev(phi), to_dev(pi))
+    src = None
+    if with_source:
+        gpu_source(eng, grid, dict(SRC, amplitude=50.0), 3)
+        src = oracle_source(g, dict(SRC, amplitude=50.0), 3)
+    w = eng.step(3)
+    p, q = eng.get_state()
+    rp, rq = phi, pi
+    rw = []
+    for n in range(3):
+        rp, rq = T.step(g, rp, rq, n, src)
+        rw.append(rp[:, g.i_ext])
+    assert rel(host(p), rp) <= 1e-13
+    assert rel(host(q), rq) <= 1e-13
+    assert rel(host(w), np.array(rw)) <= 1e-13
+
+
+def test_schwarzschild_pulse_full_run():
+    cfg = W.SCHWARZSCHILD_PULSE
+    grid, n = cfg["grid"], cfg["steps"]
+    eng = gpu_engine(grid)
+    eng.init_pulse(**cfg["pulse"])
+    w = eng.step(n)
+    p, q = eng.get_state()
+    g = T.Grid(**grid)
+    rp, rq = T.initial_pulse(g, **cfg["pulse"])
+    rp, rq, rw = T.evolve(g, rp, rq, n)
+    e = (rel(host(p), rp), rel(host(q), rq), rel(host(w), rw))
+    print("schwarzschild 801x33 x 2000 relative L2 (Phi, Pi, waveform):", e)
+    assert max(e) <= 1e-12, e
+
+
+def test_kerr_forced_run_small():
+    grid = dict(M=1.0, a=0.9, s=-2, m=2, nr=480, nth=48, rs_min=-50.0, rs_max=150.0, cfl=0.5,
+                rs_extract=100.0, ko_eps=0.5)
+    n = 1500
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    w = eng.step(n)
+    p, q = eng.get_state()
+    g = T.Grid(**grid)
+    z = np.zeros((g.nth, g.nr), np.complex128)
+    rp, rq, rw = T.evolve(g, z, z, n, oracle_source(g, SRC, n))
+    e = (rel(host(p), rp), rel(host(q), rq), rel(host(w), rw))
+    print("kerr forced 480x48 x 1500 relative L2 (Phi, Pi, waveform):", e)
+    assert max(e) <= 1e-12, e
+
+
+def test_step_calls_compose_bitwise():
+    grid = STEP_GRIDS[0]
+    phi, pi = W.random_state(grid["nth"], grid["nr"], seed=3)
+    outs = []
+    for split in ([7], [3, 4], [1, 1, 5]):
+        eng = gpu_engine(grid)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        gpu_source(eng, grid, SRC, 7)
+        ws = [host(eng.step(k)) for k in split]
+        p, q = eng.get_state()
+        outs.append((np.concatenate(ws), host(p), host(q)))
+        assert eng.info["steps_done"] == 7
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_set_get_state_roundtrip_and_extract():
+    grid = STEP_GRIDS[0]
+    phi, pi = W.random_state(grid["nth"], grid["nr"], seed=5)
+    eng = gpu_engine(grid)
+    eng.set_state(to_dev(phi), to_dev(pi))
+    p, q = eng.get_state()
+    assert np.array_equal(host(p), phi) and np.array_equal(host(q), pi)
+    assert np.array_equal(host(eng.extract()), phi[:, eng.info["i_ext"]])
+
+
+def test_orbit_too_short_is_an_error():
+    from paper_1001_3631_amd._lib import TeukError, TEUK_ESTATE
+    grid = STEP_GRIDS[0]
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, 4)          # samples for 4 iterations
+    eng.step(4)
+    with pytest.raises(TeukError) as ei:
+        eng.step(1)
+    assert ei.value.code == TEUK_ESTATE
+
+
+def test_nonfinite_state_is_detected():
+    from paper_1001_3631_amd._lib import TeukError, TEUK_ENONFINITE
+    grid = STEP_GRIDS[0]
+    phi, pi = W.random_state(grid["nth"], grid["nr"], seed=5)
+    phi[3, 17] = np.nan
+    eng = gpu_engine(grid)
+    eng.set_state(to_dev(phi), to_dev(pi))
+    with pytest.raises(TeukError) as ei:
+        eng.check_finite()
+    assert ei.value.code == TEUK_ENONFINITE
+
+
+# ---------------------------------------------------------------------------
+# Full-size forced EMRI grid (6400 x 128), the benchmarked launch configuration
+# ---------------------------------------------------------------------------
+
+def test_kerr_emri_fullsize_one_step_against_oracle():
+    """Evolve 300 iterations on the GPU, then compare one more GPU iteration
+    with one oracle iteration applied to the same GPU state (whole field)."""
+    cfg = W.KERR_EMRI
+    grid = cfg["grid"]
+    n0 = 300
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, cfg["source"], n0 + 1)
+    eng.step(n0, waveform=False)
+    p0, q0 = eng.get_state()
+    p0, q0 = host(p0), host(q0)
+    w = eng.step(1)
+    p1, q1 = eng.get_state()
+    g = T.Grid(**grid)
+    src = oracle_source(g, cfg["source"], n0 + 1)
+    rp, rq = T.step(g, p0, q0, n0, src)
+    assert np.max(np.abs(p0)) > 0
+    assert rel(host(p1), rp) <= 1e-13
+    assert rel(host(q1), rq) <= 1e-13
+    assert rel(host(w)[0], rp[:, g.i_ext]) <= 1e-13 or np.max(np.abs(rp[:, g.i_ext])) == 0
+
+
+def test_kerr_emri_fullsize_amplitude_scaling_is_exact():
+    """The evolution from zero data is linear in the source amplitude and a
+    factor 2 is exact in binary floating point: w(2A) == 2 w(A) bitwise."""
+    cfg = W.KERR_EMRI
+    grid = cfg["grid"]
+    res = []
+    for A in (1.0, 2.0):
+        eng = gpu_engine(grid)
+        gpu_source(eng, grid, dict(cfg["source"], amplitude=A), 400)
+        eng.step(400, waveform=False)
+        res.append([host(x) for x in eng.get_state()])
+    assert np.array_equal(res[1][0], 2.0 * res[0][0])
+    assert np.array_equal(res[1][1], 2.0 * res[0][1])
+    assert np.max(np.abs(res[0][0])) > 0
+
+
+def test_kerr_emri_fullsize_full_run_steady_frequency():
+    """40000 iterations: the state stays finite and, once the direct signal
+    from the circular orbit has reached r* = 500M, the extracted waveform
+    advances in phase by -m Omega dt per iteration (the system is linear and
+    time invariant and the source is periodic)."""
+    cfg = W.KERR_EMRI
+    grid = cfg["grid"]
+    n = cfg["steps"]
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, cfg["source"], n)
+    w = host(eng.step(n))
+    eng.check_finite()
+    dt = eng.info["dt"]
+    Om = 1.0 / (10.0 ** 1.5 + 0.9)
+    j = grid["nth"] // 2
+    seg = w[31000:38000, j]
+    adv = np.angle(seg[1:] / seg[:-1])
+    expect = -2 * Om * dt
+    print("phase advance per step", np.median(adv), "expected", expect)
+    assert abs(np.median(adv) - expect) <= 1e-3 * abs(expect)
+    amp = np.abs(seg)
+    assert np.std(amp) / np.mean(amp) < 0.05
