@@ -146,11 +146,23 @@ int teuk_extract_waveform(const teuk_ctx* ctx, void* out_dev);
 /* Synchronize and check that the state is finite; TEUK_ENONFINITE if not. */
 int teuk_check_finite(teuk_ctx* ctx);
 
+/* Launch configuration of the stencil (results are bitwise identical for
+ * every valid setting; only speed changes).
+ *   seg_rows  theta rows per wave segment of the streaming stencil: 4, 8 or 16.
+ *             The default is chosen from the grid size at teuk_init_grid. */
+typedef struct {
+    int32_t seg_rows;
+} teuk_tuning;
+
+int teuk_set_tuning(teuk_ctx* ctx, const teuk_tuning* t);
+int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
+
 /* Measurement aid: while enabled, every stencil launch made by teuk_step_n
- * is bracketed by a pair of HIP events on the context's stream (the source
- * pass is not).  teuk_kernel_timing synchronizes and returns the summed
- * event-to-event time of those launches (ms) and their count since timing
- * was enabled.  Enabling resets the sums. */
+ * records a pair of HIP events at the start and end of that kernel's
+ * execution (hipExtLaunchKernel; the source pass is not timed).
+ * teuk_kernel_timing synchronizes and returns the summed kernel time (ms)
+ * and the number of timed launches since timing was enabled.  Enabling
+ * resets the sums. */
 int teuk_set_kernel_timing(teuk_ctx* ctx, int enable);
 int teuk_kernel_timing(teuk_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -126,6 +126,10 @@ def coefficients(x, theta, M, a, s, m):
       C_0 = [2imas Delta' + (3 Delta/r^2)(2 Delta + (1+s) r Delta' + 2imar)] / Sigma^2
       m_r = b c_t + C_r - b d_r* b            (from eliminating Phi_t with Pi)
 
+    Polynomials that cancel at large r or vanish identically are evaluated in
+    expanded, cancellation-free forms (the same fields); "mr_def" keeps m_r
+    as written above for cross-checking.
+
     Arguments broadcast; x and theta may be arrays of compatible shapes.
     """
     rp, rm = horizons(M, a)
@@ -141,16 +145,30 @@ def coefficients(x, theta, M, a, s, m):
     Sig = np.sqrt(Sig2)
     b = q / Sig
     w = Delta / Sig2
-    ct = (4j * M * a * m * r + 2.0 * s * (r * Delta - M * (r * r - a * a))
-          + 2j * s * a * Delta * cos) / Sig2
+    # r Delta - M(r^2 - a^2) = r^2 (r - 3M) + a^2 (r + M)
+    ct_re_num = 2.0 * s * (r * r * (r - 3.0 * M) + a * a * (r + M))
+    ct = (ct_re_num + 1j * (4.0 * M * a * m * r + 2.0 * s * a * Delta * cos)) / Sig2
     Cr = (q * s * dDelta + 2.0 * r * Delta + 2j * m * a * q + 6.0 * q * Delta / r) / Sig2
+    # 2 Delta + (1+s) r Delta' = 2(2+s) r^2 - 2(3+s) M r + 2 a^2
     C0 = (2j * m * a * s * dDelta
-          + (3.0 * Delta / r ** 2) * (2.0 * Delta + (1.0 + s) * r * dDelta + 2j * m * a * r)) / Sig2
-    # d b / d r* = (Delta / q) d/dr (q / Sigma)
+          + (3.0 * Delta / r ** 2) * (2.0 * (2.0 + s) * r * r - 2.0 * (3.0 + s) * M * r + 2.0 * a * a
+                                      + 2j * m * a * r)) / Sig2
+    # m_r by its definition, b c_t + C_r - b d_r* b, with d_r* b = (Delta/q) d/dr (q/Sigma)
     dSig_dr = (4.0 * r * q - a * a * dDelta * sin2) / (2.0 * Sig)
     db_drs = (Delta / q) * (2.0 * r / Sig - q * dSig_dr / Sig2)
-    mr = b * ct + Cr - b * db_drs
-    return {"b": b, "w": w, "ct": ct, "Cr": Cr, "C0": C0, "mr": mr,
+    mr_def = b * ct + Cr - b * db_drs
+    # The same field collected over Sigma^4 so that nothing cancels (for a = 0,
+    # s = -2 it vanishes identically, and the definition above leaves ~1e-16
+    # of rounding residue that the evolution amplifies):
+    #   Re m_r Sigma^4 = q^2 Delta [4(s+2) r + 6 a^2/r]
+    #                    - a^2 Delta sin^2 [q ct_re_num/(q + Sigma) + q((s + 1/2) Delta' + 6 Delta/r)]
+    #   Im m_r = q (4Mamr + 2sa Delta cos)/Sigma^3 + 2maq/Sigma^2
+    re = (q * q * Delta * (4.0 * (s + 2.0) * r + 6.0 * a * a / r)
+          - a * a * Delta * sin2 * (q * ct_re_num / (q + Sig)
+                                    + q * ((s + 0.5) * dDelta + 6.0 * Delta / r))) / (Sig2 * Sig2)
+    im = q * (4.0 * M * a * m * r + 2.0 * s * a * Delta * cos) / (Sig2 * Sig) + 2.0 * m * a * q / Sig2
+    mr = re + 1j * im
+    return {"b": b, "w": w, "ct": ct, "Cr": Cr, "C0": C0, "mr": mr, "mr_def": mr_def,
             "r": r, "Delta": Delta, "q": q, "Sig2": Sig2}
 
 

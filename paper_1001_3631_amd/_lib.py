@@ -44,6 +44,10 @@ class Info(ctypes.Structure):
                 ("row_pitch", ctypes.c_int32), ("steps_done", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("seg_rows", ctypes.c_int32)]
+
+
 class SourceDesc(ctypes.Structure):
     _fields_ = [("amplitude", ctypes.c_double), ("sigma_r_cells", ctypes.c_double),
                 ("sigma_th_cells", ctypes.c_double), ("cutoff_sigmas", ctypes.c_double),
@@ -69,6 +73,8 @@ SIGNATURES = {
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
     "teuk_check_finite": (ctypes.c_int, [_CTX]),
+    "teuk_set_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
+    "teuk_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
     "teuk_set_kernel_timing": (ctypes.c_int, [_CTX, ctypes.c_int]),
     "teuk_kernel_timing": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),

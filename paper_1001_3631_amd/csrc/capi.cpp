@@ -48,7 +48,7 @@ struct teuk_ctx {
     ThetaRow* d_rows = nullptr;
     int* d_flag = nullptr;
     double ko_c = 0.0;
-    int nstrips = 0, nseg = 0;
+    int nstrips = 0, nseg = 0, seg_rows = 16;
     int64_t steps_done = 0;
     // source
     bool has_src = false;
@@ -150,7 +150,10 @@ int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
     c->ld = (G.nr + 15) / 16 * 16;
     c->ko_c = d->ko_eps / 16.0;
     c->nstrips = (G.nr + 61) / 62;
-    c->nseg = (G.nth - 3) / teuk::kStepSeg + 1;
+    // default segment: 8 rows when that still gives at least one wave per SIMD
+    // (256 CUs x 4 SIMDs), else 4; the autotuner refines this by measurement
+    c->seg_rows = (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= 1024) ? 8 : 4;
+    c->nseg = (G.nth - 3) / c->seg_rows + 1;
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
@@ -394,12 +397,11 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
                 c->ev_start.push_back(a);
                 c->ev_stop.push_back(b);
             }
-            HIP_TRY(hipEventRecord(c->ev_start[c->ev_used], c->stream), "event record");
-        }
-        HIP_TRY(teuk::launch_step(P, c->stream), "step kernel");
-        if (c->timing) {
-            HIP_TRY(hipEventRecord(c->ev_stop[c->ev_used], c->stream), "event record");
+            HIP_TRY(teuk::launch_step(P, c->seg_rows, c->stream, c->ev_start[c->ev_used],
+                                      c->ev_stop[c->ev_used]), "step kernel");
             c->ev_used += 1;
+        } else {
+            HIP_TRY(teuk::launch_step(P, c->seg_rows, c->stream), "step kernel");
         }
         c->cur ^= 1;
         c->steps_done += 1;
@@ -413,6 +415,22 @@ int teuk_extract_waveform(const teuk_ctx* c, void* out) {
     HIP_TRY(hipMemcpy2DAsync(out, sizeof(double2), c->plane[c->cur][0] + c->G.i_ext,
                              sizeof(double2) * c->ld, sizeof(double2), c->G.nth, hipMemcpyDeviceToDevice,
                              c->stream), "extract");
+    return TEUK_OK;
+}
+
+int teuk_set_tuning(teuk_ctx* c, const teuk_tuning* t) {
+    if (int rc = check_ctx(c)) return rc;
+    if (t == nullptr || !teuk::valid_segment_rows(t->seg_rows))
+        return fail(TEUK_EINVAL, "seg_rows must be 4, 8 or 16");
+    c->seg_rows = t->seg_rows;
+    c->nseg = (c->G.nth - 3) / c->seg_rows + 1;
+    return TEUK_OK;
+}
+
+int teuk_get_tuning(const teuk_ctx* c, teuk_tuning* out) {
+    if (int rc = check_ctx(c)) return rc;
+    if (out == nullptr) return fail(TEUK_EINVAL, "null output");
+    out->seg_rows = c->seg_rows;
     return TEUK_OK;
 }
 

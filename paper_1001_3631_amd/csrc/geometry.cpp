@@ -100,18 +100,23 @@ std::string build_geometry(double M, double a, int s, int m, int nr, int nth,
         set(RF_Q2, q * q);
         set(RF_A2D, a * a * Delta);
         set(RF_DELTA, Delta);
-        // c_t numerator: 2s(r Delta - M(r^2 - a^2)) + i(4 M a m r + 2 s a Delta cos)
-        set(RF_CT_RE, 2.0 * s * (r * Delta - M * (r * r - a * a)));
+        // c_t numerator: 2s(r Delta - M(r^2 - a^2)) + i(4 M a m r + 2 s a Delta cos),
+        // with r Delta - M(r^2 - a^2) = r^2 (r - 3M) + a^2 (r + M)
+        const double ct_re = 2.0 * s * (r * r * (r - 3.0 * M) + a * a * (r + M));
+        set(RF_CT_RE, ct_re);
         set(RF_CT_I0, 4.0 * M * a * m * r);
         set(RF_CT_I1, 2.0 * s * a * Delta);
-        // C_0 numerator: (3 Delta/r^2)(2 Delta + (1+s) r Delta') + i(2 m a s Delta' + 6 m a Delta / r)
-        set(RF_C0_RE, (3.0 * Delta / (r * r)) * (2.0 * Delta + (1.0 + s) * r * dDelta));
+        // C_0 numerator: (3 Delta/r^2)(2 Delta + (1+s) r Delta') + i(2 m a s Delta' + 6 m a Delta / r),
+        // with 2 Delta + (1+s) r Delta' = 2(2+s) r^2 - 2(3+s) M r + 2 a^2
+        set(RF_C0_RE, (3.0 * Delta / (r * r)) * (2.0 * (2.0 + s) * r * r - 2.0 * (3.0 + s) * M * r + 2.0 * a * a));
         set(RF_C0_IM, 2.0 * m * a * s * dDelta + 6.0 * m * a * Delta / r);
-        // m_r = b c_t + [q(s Delta' + 6 Delta/r) + 2 i m a q] g^2 + [2 r q^2 Delta - q Delta a^2 Delta'/2 sin^2] g^4
-        set(RF_MR_A, q * (s * dDelta + 6.0 * Delta / r));
+        // m_r = b c_t + C_r - b d_r* b collected over Sigma^4:
+        //   Re: q^2 Delta [4(s+2) r + 6 a^2/r] - a^2 Delta sin^2 [q ct_re/(q + Sigma) + q((s+1/2) Delta' + 6 Delta/r)]
+        //   Im: b Im(c_t) + 2 m a q / Sigma^2
+        set(RF_MR_P, q * q * Delta * (4.0 * (s + 2.0) * r + 6.0 * a * a / r));
         set(RF_MR_B, 2.0 * m * a * q);
-        set(RF_MR_C, 2.0 * r * q * q * Delta);
-        set(RF_MR_D, 0.5 * q * Delta * a * a * dDelta);
+        set(RF_MR_K1, q * ct_re);
+        set(RF_MR_K2, q * ((s + 0.5) * dDelta + 6.0 * Delta / r));
         set(RF_RS, rs);
     };
     for (int i = 0; i < nr; ++i) fill(G.rnode, i, rs_min + i * G.h_r);
@@ -127,15 +132,15 @@ std::string build_geometry(double M, double a, int s, int m, int nr, int nth,
         ThetaRow& R = G.rows[j];
         const double th = j * hh;
         R.theta = th;
+        R.inv_h2 = 1.0 / (hh * hh);
         R.cos_th = std::cos(th);
         const double sn = std::sin(th);
         R.sin2 = sn * sn;
         if (j > 0 && j < nth - 1) {
             const double cot = R.cos_th / sn;
             const double V = (m + s * R.cos_th) * (m + s * R.cos_th) / (sn * sn) - s;
-            R.alpha = 1.0 / (hh * hh) + cot / (2.0 * hh);
-            R.beta = -2.0 / (hh * hh) - V;
-            R.gamma = 1.0 / (hh * hh) - cot / (2.0 * hh);
+            R.cot2h = cot / (2.0 * hh);
+            R.V = V;
         }
         R.prof = std::pow(2.0, 0.5 * (p + qq)) * std::pow(std::sin(0.5 * th), p) *
                  std::pow(std::cos(0.5 * th), qq);

@@ -9,9 +9,12 @@
 //   w   = Delta g^2
 //   c_t = [ct_re + i (ct_i0 + ct_i1 cos)] g^2
 //   C_0 = [c0_re + i c0_im] g^2
-//   m_r = b c_t + (mr_a + i mr_b) g^2 + (mr_c - mr_d sin^2) g^4
+//   Re m_r = [mr_p - a^2 Delta sin^2 (mr_k1/(q + Sigma) + mr_k2)] g^4
+//   Im m_r = b Im c_t + mr_b g^2
 // so the device keeps one radial record per node / half node and one angular
-// record per row, and forms the 2D fields on the fly.
+// record per row, and forms the 2D fields on the fly.  The numerators are
+// written in expanded forms that do not cancel: m_r vanishes identically for
+// a = 0, s = -2, and cancellation residue there is amplified by the evolution.
 #pragma once
 
 #include <cstdint>
@@ -23,20 +26,21 @@ namespace teuk {
 // Fields of one radial record (struct-of-arrays on the device, in this order).
 enum RField {
     RF_Q = 0, RF_Q2, RF_A2D, RF_DELTA, RF_CT_RE, RF_CT_I0, RF_CT_I1,
-    RF_C0_RE, RF_C0_IM, RF_MR_A, RF_MR_B, RF_MR_C, RF_MR_D, RF_RS,
+    RF_C0_RE, RF_C0_IM, RF_MR_P, RF_MR_B, RF_MR_K1, RF_MR_K2, RF_RS,
     RF_COUNT
 };
 
 // One angular record per row (array-of-structs, 8 doubles = 64 bytes).
+// Pole rows (j = 0, nth-1) leave cot2h and V at zero: they are never evolved.
 struct ThetaRow {
     double cos_th;   // cos(theta_j)
     double sin2;     // sin^2(theta_j)
-    double alpha;    // weight of f_{j+1} in Ang[f]_j: 1/h^2 + cot/(2h)
-    double beta;     // weight of f_j: -2/h^2 - V_j
-    double gamma;    // weight of f_{j-1}: 1/h^2 - cot/(2h)
+    double cot2h;    // cot(theta_j) / (2 h_th)
+    double V;        // angular potential (m + s cos)^2 / sin^2 - s
+    double inv_h2;   // 1 / h_th^2
     double theta;    // theta_j
     double prof;     // initial angular profile P(theta_j)
-    double pad;
+    double pad;      // keeps the record at 64 bytes
 };
 
 struct Geometry {

@@ -7,8 +7,8 @@
 
 namespace teuk {
 
-// Rows of theta per wave segment in the streaming stencil.
-constexpr int kStepSeg = 16;
+// Rows of theta per wave segment in the streaming stencil (compiled variants).
+constexpr int kSegVariants[] = {4, 8, 16};
 
 struct StepParams {
     const double2* phi;         // u^n planes [nth][ld]
@@ -57,8 +57,9 @@ struct PulseParams {
     int even;
 };
 
-int step_segment_rows();
-hipError_t launch_step(const StepParams& P, hipStream_t stream);
+bool valid_segment_rows(int seg);
+hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream);
 hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream);
 hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,

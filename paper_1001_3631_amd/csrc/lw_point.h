@@ -13,7 +13,7 @@ namespace teuk {
 
 // Radial record of one column (node or half node), see geometry.h.
 struct RCol {
-    double q, q2, a2d, delta, ct_re, ct_i0, ct_i1, c0_re, c0_im, mr_a, mr_b, mr_c, mr_d;
+    double q, q2, a2d, delta, ct_re, ct_i0, ct_i1, c0_re, c0_im, mr_p, mr_b, mr_k1, mr_k2;
 };
 
 __device__ __forceinline__ RCol load_rcol(const double* __restrict__ tab, int pitch, int i) {
@@ -27,10 +27,10 @@ __device__ __forceinline__ RCol load_rcol(const double* __restrict__ tab, int pi
     r.ct_i1 = tab[RF_CT_I1 * pitch + i];
     r.c0_re = tab[RF_C0_RE * pitch + i];
     r.c0_im = tab[RF_C0_IM * pitch + i];
-    r.mr_a = tab[RF_MR_A * pitch + i];
+    r.mr_p = tab[RF_MR_P * pitch + i];
     r.mr_b = tab[RF_MR_B * pitch + i];
-    r.mr_c = tab[RF_MR_C * pitch + i];
-    r.mr_d = tab[RF_MR_D * pitch + i];
+    r.mr_k1 = tab[RF_MR_K1 * pitch + i];
+    r.mr_k2 = tab[RF_MR_K2 * pitch + i];
     return r;
 }
 
@@ -40,8 +40,10 @@ struct Coef {
     double2 ct, mr, c0;
 };
 
-// b = q g, w = Delta g^2, c_t, C_0 = numerators g^2,
-// m_r = b c_t + (mr_a + i mr_b) g^2 + (mr_c - mr_d sin^2) g^4, g = 1/Sigma.
+// b = q g, w = Delta g^2, c_t, C_0 = numerators g^2, g = 1/Sigma,
+// Re m_r = [mr_p - a^2 Delta sin^2 (mr_k1/(q + Sigma) + mr_k2)] g^4,
+// Im m_r = b Im c_t + mr_b g^2.  For a = 0 the bracket's second term is zero
+// and the division is skipped.
 __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin2) {
     const double sig2 = fma(-r.a2d, sin2, r.q2);
     const double g = rsqrt(sig2);
@@ -54,8 +56,12 @@ __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin
     c.ct.y = fma(r.ct_i1, cos_th, r.ct_i0) * g2;
     c.c0.x = r.c0_re * g2;
     c.c0.y = r.c0_im * g2;
-    const double e = fma(-r.mr_d, sin2, r.mr_c) * g4;
-    c.mr.x = fma(c.b, c.ct.x, fma(r.mr_a, g2, e));
+    double num = r.mr_p;
+    if (r.a2d != 0.0) {
+        const double inv_qs = 1.0 / fma(sig2, g, r.q);   // 1/(q + Sigma), Sigma = Sigma^2 g
+        num = fma(-r.a2d * sin2, fma(r.mr_k1, inv_qs, r.mr_k2), num);
+    }
+    c.mr.x = num * g4;
     c.mr.y = fma(c.b, c.ct.y, r.mr_b * g2);
     return c;
 }
@@ -76,8 +82,10 @@ __device__ __forceinline__ double2 c_scale(double s, double2 a) { return make_do
 //   Phi'  = basePhi + tau (Pi~ - b dPhi)          (S_Phi = Pi~, D = diag(b, -b))
 //   Pi'   = basePi  + tau (b dPi + S_Pi)
 // Half step (lw1): tau = dt/2, base = (Phi~, Pi~).  Full step (lw2): tau = dt,
-// base = u^n at the node.  Ang_h[f]_j = alpha f_{j+1} + beta f_j + gamma f_{j-1}.
-__device__ __forceinline__ void lw_point(const Coef& c, double alpha, double beta, double gamma,
+// base = u^n at the node.  Ang_h[f]_j = (f_{j+1} - 2 f_j + f_{j-1})/h^2
+// + cot (f_{j+1} - f_{j-1})/(2h) - V f_j, differences taken first (the
+// second difference of a smooth field is small; weighting first would cancel).
+__device__ __forceinline__ void lw_point(const Coef& c, const ThetaRow& R,
                                          double2 sPm, double2 sP0, double2 sPp, double2 sQ0,
                                          double2 dP0, double2 dQ0, double2 F,
                                          double tau, double inv_hr,
@@ -88,8 +96,12 @@ __device__ __forceinline__ void lw_point(const Coef& c, double alpha, double bet
     const double2 dP = c_scale(inv_hr, dP0);
     const double2 dQ = c_scale(inv_hr, dQ0);
     double2 ang;
-    ang.x = 0.5 * fma(alpha, sPp.x, fma(beta, sP0.x, gamma * sPm.x));
-    ang.y = 0.5 * fma(alpha, sPp.y, fma(beta, sP0.y, gamma * sPm.y));
+    {
+        const double d2x = (sPp.x - 2.0 * sP0.x) + sPm.x, d2y = (sPp.y - 2.0 * sP0.y) + sPm.y;
+        const double d1x = sPp.x - sPm.x, d1y = sPp.y - sPm.y;
+        ang.x = 0.5 * fma(-R.V, sP0.x, fma(R.cot2h, d1x, d2x * R.inv_h2));
+        ang.y = 0.5 * fma(-R.V, sP0.y, fma(R.cot2h, d1y, d2y * R.inv_h2));
+    }
     double2 S;
     S.x = fma(c.w, ang.x, F.x);
     S.y = fma(c.w, ang.y, F.y);
@@ -125,9 +137,12 @@ __device__ __forceinline__ double2 ko_apply(double2 out, double ko_c, double2 um
 }
 
 // Pole rows from the boundary condition: (4 u_1 - u_2)/3 (even |m|), 0 (odd |m|).
+// The third is a multiplication by the rounded 1/3 (a division would expand
+// into a long instruction sequence).
 __device__ __forceinline__ double2 pole_value(bool even, double2 u1, double2 u2) {
     if (!even) return make_double2(0.0, 0.0);
-    return make_double2(fma(4.0, u1.x, -u2.x) / 3.0, fma(4.0, u1.y, -u2.y) / 3.0);
+    const double third = 0.33333333333333331483;   // nearest double to 1/3
+    return make_double2(fma(4.0, u1.x, -u2.x) * third, fma(4.0, u1.y, -u2.y) * third);
 }
 
 // Synthetic source value at (t, r*, theta): amplitude G_r G_th e^{-i m phi~_p}.

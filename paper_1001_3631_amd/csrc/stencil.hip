@@ -6,6 +6,7 @@
 // Coefficients are never stored as 2D fields: each wave keeps the radial
 // records of its 64 columns in registers and forms b, w, c_t, m_r, C_0 per
 // point from them and one angular record per row (see geometry.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                     const ThetaRow R = P.rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2);
                     const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
-                    lw_point(c, R.alpha, R.beta, R.gamma, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
+                    lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
                              dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
                              c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
                 } else if (jh == nth - 1 && t >= 4) {
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                         const double2 sQ0 = c_add(hQ[t - 2], gQ[t - 2]);
                         const double2 dP0 = c_sub(hP[t - 2], gP[t - 2]);
                         const double2 dQ0 = c_sub(hQ[t - 2], gQ[t - 2]);
-                        lw_point(c, R.alpha, R.beta, R.gamma, sPm, sP0, sPp, sQ0, dP0, dQ0, F,
+                        lw_point(c, R, sPm, sP0, sPp, sQ0, dP0, dQ0, F,
                                  P.dt, P.inv_hr, uP[t - 2], uQ[t - 2], oP, oQ);
                         if (P.ko_c != 0.0) {
                             const double sg = P.even ? 1.0 : -1.0;
@@ -285,12 +286,24 @@ __global__ void __launch_bounds__(256) finite_kernel(const double2* __restrict__
 // Host-side launchers
 // ---------------------------------------------------------------------------
 
-int step_segment_rows() { return kStepSeg; }
+bool valid_segment_rows(int seg) {
+    for (int v : kSegVariants)
+        if (v == seg) return true;
+    return false;
+}
 
-hipError_t launch_step(const StepParams& P, hipStream_t stream) {
+// P.nseg must have been computed for this segment length: (nth - 3) / seg + 1.
+// With events, the launch itself records them at the kernel's start and end.
+hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start,
+                       hipEvent_t ev_stop) {
     const int items = P.nstrips * P.nseg;
-    const int blocks = (items + 3) / 4;
-    hipLaunchKernelGGL(lw_step_kernel<kStepSeg>, dim3(blocks), dim3(256), 0, stream, P);
+    const dim3 grid((items + 3) / 4), block(256);
+    switch (seg) {
+        case 4: hipExtLaunchKernelGGL(lw_step_kernel<4>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
+        case 8: hipExtLaunchKernelGGL(lw_step_kernel<8>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
+        case 16: hipExtLaunchKernelGGL(lw_step_kernel<16>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -134,6 +134,16 @@ class Engine:
         L.check(self._lib.teuk_extract_waveform(self.ctx, _ptr(w)))
         return w
 
+    @property
+    def tuning(self):
+        t = L.Tuning()
+        L.check(self._lib.teuk_get_tuning(self.ctx, ctypes.byref(t)))
+        return {"seg_rows": t.seg_rows}
+
+    def set_tuning(self, seg_rows):
+        t = L.Tuning(int(seg_rows))
+        L.check(self._lib.teuk_set_tuning(self.ctx, ctypes.byref(t)))
+
     def set_kernel_timing(self, enable):
         L.check(self._lib.teuk_set_kernel_timing(self.ctx, 1 if enable else 0))
 

@@ -131,6 +131,7 @@ def test_first_order_momentum_coefficient(M, a, s, m):
             c = T.coefficients(x, th, M, a, s, m)
             expect = complex(b_of_r(r0) * (mp.mpc(c["ct"]) ) + mp.mpc(c["Cr"]) - b_of_r(r0) * db_drs)
             assert abs(complex(c["mr"]) - expect) <= 1e-13 * max(1.0, abs(expect)) + 1e-15
+            assert abs(complex(c["mr_def"]) - expect) <= 1e-13 * max(1.0, abs(expect)) + 1e-15
 
 
 def test_schwarzschild_closed_forms():
@@ -144,7 +145,8 @@ def test_schwarzschild_closed_forms():
     np.testing.assert_allclose(c["b"], 1.0, rtol=1e-15)
     np.testing.assert_allclose(c["ct"].real, -4 * (r - 3 * M) / r ** 2, rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(c["ct"].imag, 0.0, atol=0)
-    np.testing.assert_allclose(c["mr"], 0.0, atol=1e-13)
+    assert np.all(c["mr"] == 0.0)           # the cancellation-free form is exactly zero
+    np.testing.assert_allclose(c["mr_def"], 0.0, atol=1e-13)
     np.testing.assert_allclose(c["C0"].real, -6 * M * Delta / r ** 5, rtol=1e-11, atol=1e-18)
     np.testing.assert_allclose(c["w"], Delta / r ** 4, rtol=1e-12)
 
