@@ -38,7 +38,25 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
     ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--iterations", type=int, default=None,
+                    help="override the iterations per evolution (profiling passes only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain elementwise kernel of known traffic: read 256 MiB, write 256 MiB."""
+    import torch
+    n = 16 * 1024 * 1024                      # complex128 elements = 256 MiB
+    a = torch.ones(n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"kernel": "elementwise mul (torch)", "dispatches": 3,
+                                           "read_bytes_per_dispatch": n * 16,
+                                           "write_bytes_per_dispatch": n * 16}}), flush=True)
 
 
 def make_engine(cfg, nsteps):
@@ -77,6 +95,9 @@ def cpu_baseline(cfg, iters):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note only)"}))
@@ -87,7 +108,7 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     cfg = W.KERR_EMRI
     g = cfg["grid"]
-    n = cfg["steps"]
+    n = args.iterations or cfg["steps"]
     npts = g["nr"] * g["nth"]
     eng = make_engine(cfg, n)
     zphi = torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda")
