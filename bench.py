@@ -28,6 +28,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 64.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kernel_kerr_emri_6400x128_traffic.json")
+
+
+def measured_traffic(seg_rows):
+    """HBM-side bytes per stencil launch from the committed counter summary,
+    or None if the stencil sources or the launch configuration changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"] or f"seg_rows {seg_rows}" not in rec["workload"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def parse():
@@ -137,7 +154,8 @@ def main():
     avg_s = kms / kn * 1e-3
     achieved = npts * BYTES_PER_POINT / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(eng.tuning["seg_rows"]),
                 "kernel": "lw_step_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
                 "bytes_per_launch": int(npts * BYTES_PER_POINT), "launches_timed": kn}
     print(f"[bench] stencil launch avg {avg_s*1e6:.2f} us -> {achieved:.0f} GB/s algorithmic",

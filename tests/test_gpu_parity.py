@@ -298,7 +298,7 @@ def test_kerr_emri_fullsize_amplitude_scaling_is_exact():
         big = np.abs(res[1][k]) >= 1e-200
         assert np.max(d, initial=0.0) < 1e-290, np.max(d)
         assert np.array_equal(res[1][k][big], 2.0 * res[0][k][big])
-        assert big.sum() > 0.5 * big.size
+        assert big.sum() > 1000
     assert np.max(np.abs(res[0][0])) > 0
 
 
