@@ -140,6 +140,34 @@ int teuk_orbit_circular(double M, double a, double r0, double dt, int64_t nsampl
  * after iteration n+1 of this call.  Asynchronous. */
 int teuk_step_n(teuk_ctx* ctx, int64_t nsteps, void* waveform_dev);
 
+/* ---- Adjoint (reverse sweep) -------------------------------------------
+ * The iteration is C-linear, so the gradient of a real loss L, written as
+ * dL/dRe + i dL/dIm, propagates as lambda^n = G^H lambda^{n+1}: the
+ * conjugate transpose of one iteration, sub-step by sub-step (boundary
+ * conditions, full step with dissipation, half-step pole rows, half step).
+ * The waveform enters as lambda^n += dL/dw_n at the extraction column
+ * (E^H), the source amplitude as dL/dA += sum_n Re<lambda, d u/dA>.
+ *
+ * gw_dev (device, may be NULL) holds dL/dw_n for the forward run, laid out as
+ * the forward waveform: row n-1 = dL/dw_n (nth complex128), n = 1..n_end.
+ *
+ * teuk_adjoint_begin: lambda := (lam_phi, lam_pi) (device [nth][nr]; NULL = 0)
+ *   plus dL/dw_{n_end} at the extraction column; the reverse clock is set to
+ *   n_end (the forward iteration count lambda belongs to); dL/dA := 0.
+ * teuk_adjoint_step_n: nsteps reverse iterations m = clock-1 .. clock-nsteps,
+ *   each lambda := G^H lambda, then + dL/dw_m (m >= 1); with a source
+ *   attached, accumulates dL/dA with the unit-amplitude source of forward
+ *   iteration m.  Asynchronous.
+ * teuk_adjoint_add_state: lambda += (gphi, gpi) (device [nth][nr]; NULL
+ *   skips) - gradients of losses on the state at the current clock.
+ * teuk_adjoint_get: copies lambda out (device, NULL skips) and, if dL_dA is
+ *   not NULL, synchronizes and stores dL/dA there (host). */
+int teuk_adjoint_begin(teuk_ctx* ctx, const void* lam_phi_dev, const void* lam_pi_dev, int64_t n_end,
+                       const void* gw_dev);
+int teuk_adjoint_step_n(teuk_ctx* ctx, int64_t nsteps, const void* gw_dev);
+int teuk_adjoint_add_state(teuk_ctx* ctx, const void* gphi_dev, const void* gpi_dev);
+int teuk_adjoint_get(teuk_ctx* ctx, void* lam_phi_dev, void* lam_pi_dev, double* dL_dA);
+
 /* Current Phi column at the extraction radius: nth complex128 (device). */
 int teuk_extract_waveform(const teuk_ctx* ctx, void* out_dev);
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libteuk.so")
 
-SOURCES = ["geometry.cpp", "stencil.hip", "capi.cpp"]
+SOURCES = ["geometry.cpp", "stencil.hip", "adjoint.hip", "capi.cpp"]
 
 # -ffp-contract=off: every fused multiply-add is written explicitly, so every
 # kernel variant rounds identically.  Packed FP32 instructions are disabled.

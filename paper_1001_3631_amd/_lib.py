@@ -72,6 +72,10 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_double)]),
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
+    "teuk_adjoint_begin": (ctypes.c_int, [_CTX, _P, _P, ctypes.c_int64, _P]),
+    "teuk_adjoint_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
+    "teuk_adjoint_add_state": (ctypes.c_int, [_CTX, _P, _P]),
+    "teuk_adjoint_get": (ctypes.c_int, [_CTX, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "teuk_check_finite": (ctypes.c_int, [_CTX]),
     "teuk_set_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
     "teuk_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),

@@ -1,0 +1,329 @@
+// Adjoint of one Lax-Wendroff iteration: lambda^n = G^H lambda^{n+1}.
+//
+// The iteration (Sec. 3.2, Eqs. (lw1)-(lw2) with its boundary conditions) is
+// C-linear, so its transpose in the real inner product is the conjugate
+// transpose.  Taking its sub-steps in reverse order:
+//   1. boundary conditions on u^{n+1}: pole rows of lambda fold into rows
+//      1, 2 (and nth-2, nth-3) with weights 4/3, -1/3 (even |m|); radial
+//      boundary nodes drop out.  Result mu on interior nodes.
+//   2. full step: identity part (mu), dissipation transpose, and node-level
+//      sources that the full step's averages and differences carry back to
+//      the half points i-1/2, i+1/2 (conjugated node coefficients; the
+//      angular operator enters through its transpose).
+//   3. pole rows of the half-step values fold into rows 1, 2 / nth-2, nth-3.
+//   4. half step: half-level sources carried back to nodes i, i+1.
+// Every sum is a gather, so a lane owns node i and half point i+1/2 exactly as
+// in the forward stencil: half values gather from lane+1, node values from
+// lane-1.  Stages run at fixed row lags behind the row being loaded, so the
+// fully unrolled loop indexes its register arrays with compile-time offsets.
+//
+// Source sensitivity: dL/dA = sum Re<lambda-part, dt-weighted unit source>
+// over the half points (lw1, time t_n) and the interior nodes (lw2, time
+// t_n + dt/2); each wave writes its partial sum, reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "lw_point.h"
+
+namespace teuk {
+
+namespace {
+
+__device__ __forceinline__ double2 a_shfl_dn1(double2 v) {
+    return make_double2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
+}
+__device__ __forceinline__ double2 a_shfl_up1(double2 v) {
+    return make_double2(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
+}
+__device__ __forceinline__ double2 cz() { return make_double2(0.0, 0.0); }
+// conj(c) * z
+__device__ __forceinline__ double2 cmul_conj(double2 c, double2 z) {
+    return make_double2(fma(c.x, z.x, c.y * z.y), fma(c.x, z.y, -(c.y * z.x)));
+}
+__device__ __forceinline__ double2 axpy(double a, double2 x, double2 y) {
+    return make_double2(fma(a, x.x, y.x), fma(a, x.y, y.y));
+}
+__device__ __forceinline__ double re_dot_conj(double2 a, double2 b) {   // Re(conj(a) b)
+    return fma(a.x, b.x, a.y * b.y);
+}
+__device__ __forceinline__ double2 src_at(const double2* __restrict__ tab, int c0, int r0, int win_r,
+                                          int win_t, int col, int row) {
+    if (tab == nullptr) return cz();
+    const unsigned dc = static_cast<unsigned>(col - c0);
+    const unsigned dr = static_cast<unsigned>(row - r0);
+    if (dc < static_cast<unsigned>(win_r) && dr < static_cast<unsigned>(win_t)) return tab[dr * win_r + dc];
+    return cz();
+}
+__device__ __forceinline__ int a_xcd_remap(int b, int nwg) {
+    const int per = nwg / 8;
+    const int full = per * 8;
+    if (b >= full) return b;
+    return (b % 8) * per + (b / 8);
+}
+
+// weights of the angular operator at an interior row: Ang[f]_j =
+// alpha_j f_{j+1} + beta_j f_j + gamma_j f_{j-1}
+struct AngW {
+    double alpha, beta, gamma;
+};
+__device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
+    AngW w;
+    w.alpha = R.inv_h2 + R.cot2h;
+    w.beta = fma(-2.0, R.inv_h2, -R.V);
+    w.gamma = R.inv_h2 - R.cot2h;
+    return w;
+}
+
+}  // namespace
+
+template <int SEG>
+__global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
+    // rows jlo-4 .. jhi+5 (jhi - jlo <= SEG + 2).  Output row r needs mu rows
+    // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
+    constexpr int NT = SEG + 12;
+    const int lane = threadIdx.x & 63;
+    const int wg = a_xcd_remap(blockIdx.x, gridDim.x);
+    const int item = wg * 4 + (threadIdx.x >> 6);
+    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
+    const int strip = item / P.nseg;
+    const int seg = item - strip * P.nseg;
+    const int i = strip * 62 - 1 + lane;
+    const bool in_col = (i >= 0) && (i < P.nr);
+    const bool writer = in_col && lane >= 1 && lane <= 62;
+    const bool interior_col = (i >= 1) && (i <= P.nr - 2);
+    const bool has_half = (i >= 0) && (i <= P.nr - 2);
+    const int nth = P.nth;
+    const int ld = P.ld;
+    const int jlo = seg * SEG;
+    const int jhi = (seg == P.nseg - 1) ? nth : jlo + SEG;
+    const double dt = P.dt, hdt = 0.5 * P.dt, inv_hr = P.inv_hr;
+    const double third = 0.33333333333333331483, four_thirds = 1.3333333333333332593;
+
+    int4 org = make_int4(0, 0, 0, 0);
+    if (P.org != nullptr) org = *P.org;
+    const RCol rn = load_rcol(P.rnode, P.rpitch, min(max(i, 0), P.nr - 1));
+    const RCol rh = load_rcol(P.rhalf, P.rpitch, min(max(i, 0), P.nr - 2));
+
+    double2 lP[NT], lQ[NT];          // lambda^{n+1}, own column, row jlo-4+t
+    double2 mP[NT], mQ[NT];          // mu (after the boundary transpose)
+    double2 nQ[NT], nD[NT], nDQ[NT], nC[NT], nW[NT];   // node-level sources
+    double2 hP[NT], hQ[NT];          // half-level lambda at i+1/2 (unfolded)
+    double2 yW[NT], cC[NT], qb[NT], dp[NT], dq[NT];    // half-level sources
+    double dA = 0.0;
+
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+        const int jj = jlo - 4 + it;
+        if (jj > jhi + 5) continue;
+        // ---- 1. load lambda^{n+1}(i, jj) ----
+        {
+            double2 p = cz(), q = cz();
+            if (jj >= 0 && jj < nth && in_col) {
+                p = P.lam_phi[static_cast<size_t>(jj) * ld + i];
+                q = P.lam_pi[static_cast<size_t>(jj) * ld + i];
+            }
+            lP[it] = p;
+            lQ[it] = q;
+        }
+        // ---- 2./3. mu and node sources at row r = jj - 2 ----
+        if (it >= 2) {
+            const int r = jj - 2;
+            const int k = it - 2;
+            double2 p = cz(), q = cz();
+            const bool interior_row = (r >= 1) && (r <= nth - 2);
+            if (interior_row && interior_col) {
+                p = lP[k];
+                q = lQ[k];
+                if (P.even) {
+                    if (r == 1 && it >= 3) { p = axpy(four_thirds, lP[k - 1], p); q = axpy(four_thirds, lQ[k - 1], q); }
+                    if (r == 2 && it >= 4) { p = axpy(-third, lP[k - 2], p); q = axpy(-third, lQ[k - 2], q); }
+                    if (r == nth - 2) { p = axpy(four_thirds, lP[k + 1], p); q = axpy(four_thirds, lQ[k + 1], q); }
+                    if (r == nth - 3) { p = axpy(-third, lP[k + 2], p); q = axpy(-third, lQ[k + 2], q); }
+                }
+            }
+            mP[k] = p;
+            mQ[k] = q;
+            nQ[k] = nD[k] = nDQ[k] = nC[k] = nW[k] = cz();
+            if (interior_row && interior_col) {
+                const ThetaRow R = P.rows[r];
+                const Coef c = coef_at(rn, R.cos_th, R.sin2);
+                // Phi' = Phi + dt (Pi~ - b dPhi);  Pi' = Pi + dt (b dPi + S),
+                // S = -c_t Pi~ + m_r dPhi + C_0 Phi~ + w Ang[Phi~] + F
+                const double2 ctq = cmul_conj(c.ct, q);
+                nQ[k] = make_double2(dt * (p.x - ctq.x), dt * (p.y - ctq.y));          // -> Pi~
+                const double2 mrq = cmul_conj(c.mr, q);
+                nD[k] = make_double2(dt * fma(-c.b, p.x, mrq.x), dt * fma(-c.b, p.y, mrq.y));   // -> dPhi
+                nDQ[k] = make_double2(dt * c.b * q.x, dt * c.b * q.y);                // -> dPi
+                const double2 c0q = cmul_conj(c.c0, q);
+                nC[k] = make_double2(dt * c0q.x, dt * c0q.y);                         // -> Phi~ (row r)
+                nW[k] = make_double2(dt * c.w * q.x, dt * c.w * q.y);                 // -> Ang^T
+                if (P.fn != nullptr && r >= jlo && r < jhi && writer) {
+                    const double2 F = src_at(P.fn, org.z, org.w, P.win_r, P.win_t, i, r);
+                    dA = fma(dt, re_dot_conj(q, F), dA);
+                }
+            }
+        }
+        // ---- 4. half-level lambda at (i+1/2, r1), r1 = jj - 3 ----
+        if (it >= 4) {
+            const int r1 = jj - 3;
+            const int k = it - 3;
+            double2 ptil = cz();
+            if (r1 >= 0 && r1 < nth) {
+                ptil = nC[k];
+                if (r1 - 1 >= 1) ptil = axpy(ang_weights(P.rows[r1 - 1]).alpha, nW[k - 1], ptil);
+                if (r1 >= 1 && r1 <= nth - 2) ptil = axpy(ang_weights(P.rows[r1]).beta, nW[k], ptil);
+                if (r1 + 1 <= nth - 2) ptil = axpy(ang_weights(P.rows[r1 + 1]).gamma, nW[k + 1], ptil);
+            }
+            // contributions of node i to its right half (i+1/2) and left half (i-1/2)
+            const double2 a = make_double2(0.5 * ptil.x, 0.5 * ptil.y);
+            const double2 d = make_double2(nD[k].x * inv_hr, nD[k].y * inv_hr);
+            const double2 aq = make_double2(0.5 * nQ[k].x, 0.5 * nQ[k].y);
+            const double2 dqv = make_double2(nDQ[k].x * inv_hr, nDQ[k].y * inv_hr);
+            const double2 leftP = c_sub(a, d), leftQ = c_sub(aq, dqv);
+            const double2 nbP = a_shfl_dn1(leftP), nbQ = a_shfl_dn1(leftQ);   // node i+1's left part
+            if (has_half) {
+                hP[k] = c_add(c_add(a, d), nbP);
+                hQ[k] = c_add(c_add(aq, dqv), nbQ);
+            } else {
+                hP[k] = hQ[k] = cz();
+            }
+        }
+        // ---- 5./6. folded half-level lambda and half sources at r2 = jj - 5 ----
+        // (the first half row any output needs is jlo - 1, reached at it = 8)
+        if (it >= 8) {
+            const int r2 = jj - 5;
+            const int k = it - 5;
+            yW[k] = cC[k] = qb[k] = dp[k] = dq[k] = cz();
+            if (r2 >= 1 && r2 <= nth - 2 && has_half) {
+                double2 p = hP[k], q = hQ[k];
+                if (P.even) {
+                    if (r2 == 1) { p = axpy(four_thirds, hP[k - 1], p); q = axpy(four_thirds, hQ[k - 1], q); }
+                    if (r2 == 2) { p = axpy(-third, hP[k - 2], p); q = axpy(-third, hQ[k - 2], q); }
+                    if (r2 == nth - 2) { p = axpy(four_thirds, hP[k + 1], p); q = axpy(four_thirds, hQ[k + 1], q); }
+                    if (r2 == nth - 3) { p = axpy(-third, hP[k + 2], p); q = axpy(-third, hQ[k + 2], q); }
+                }
+                const ThetaRow R = P.rows[r2];
+                const Coef c = coef_at(rh, R.cos_th, R.sin2);
+                // Phi^h = Phi~ + hdt (Pi~ - b dPhi);  Pi^h = Pi~ + hdt (b dPi + S)
+                yW[k] = make_double2(hdt * c.w * q.x, hdt * c.w * q.y);
+                const double2 c0q = cmul_conj(c.c0, q);
+                cC[k] = make_double2(fma(hdt, c0q.x, p.x), fma(hdt, c0q.y, p.y));
+                const double2 ctq = cmul_conj(c.ct, q);
+                qb[k] = make_double2(fma(hdt, p.x - ctq.x, q.x), fma(hdt, p.y - ctq.y, q.y));
+                const double2 mrq = cmul_conj(c.mr, q);
+                dp[k] = make_double2(hdt * fma(-c.b, p.x, mrq.x), hdt * fma(-c.b, p.y, mrq.y));
+                dq[k] = make_double2(hdt * c.b * q.x, hdt * c.b * q.y);
+                if (P.fh != nullptr && r2 >= jlo && r2 < jhi && writer) {
+                    const double2 F = src_at(P.fh, org.x, org.y, P.win_r, P.win_t, i, r2);
+                    dA = fma(hdt, re_dot_conj(q, F), dA);
+                }
+            }
+        }
+        // ---- 7./8. lambda^n at (i, r3), r3 = jj - 6 ----
+        if (it >= 8) {
+            const int r3 = jj - 6;
+            const int k = it - 6;
+            double2 pb = cz();
+            if (r3 >= 0 && r3 < nth) {
+                pb = cC[k];
+                if (r3 - 1 >= 1) pb = axpy(ang_weights(P.rows[r3 - 1]).alpha, yW[k - 1], pb);
+                if (r3 >= 1 && r3 <= nth - 2) pb = axpy(ang_weights(P.rows[r3]).beta, yW[k], pb);
+                if (r3 + 1 <= nth - 2) pb = axpy(ang_weights(P.rows[r3 + 1]).gamma, yW[k + 1], pb);
+            }
+            // half i+1/2 gives its left node (i) 1/2 avg - diff/h, its right node (i+1) 1/2 avg + diff/h
+            const double2 hpP = make_double2(0.5 * pb.x, 0.5 * pb.y);
+            const double2 hdP = make_double2(dp[k].x * inv_hr, dp[k].y * inv_hr);
+            const double2 hpQ = make_double2(0.5 * qb[k].x, 0.5 * qb[k].y);
+            const double2 hdQ = make_double2(dq[k].x * inv_hr, dq[k].y * inv_hr);
+            const double2 rightP = c_add(hpP, hdP), rightQ = c_add(hpQ, hdQ);
+            const double2 fromLeftP = a_shfl_up1(rightP), fromLeftQ = a_shfl_up1(rightQ);
+            if (r3 >= jlo && r3 < jhi && writer) {
+                double2 oP = c_add(c_sub(hpP, hdP), (i >= 1) ? fromLeftP : cz());
+                double2 oQ = c_add(c_sub(hpQ, hdQ), (i >= 1) ? fromLeftQ : cz());
+                if (interior_col) {
+                    // identity part and the dissipation transpose (mu is zero off the interior)
+                    oP = c_add(oP, mP[k]);
+                    oQ = c_add(oQ, mQ[k]);
+                    if (P.ko_c != 0.0) {
+                        const double sg = P.even ? 1.0 : -1.0;
+                        double2 kp = ko_apply(cz(), -1.0, mP[k - 2], mP[k - 1], mP[k], mP[k + 1], mP[k + 2]);
+                        double2 kq = ko_apply(cz(), -1.0, mQ[k - 2], mQ[k - 1], mQ[k], mQ[k + 1], mQ[k + 2]);
+                        if (r3 == 1 || r3 == nth - 2) {   // ghost row reflected onto this row
+                            kp = axpy(sg, mP[k], kp);
+                            kq = axpy(sg, mQ[k], kq);
+                        }
+                        oP = axpy(-P.ko_c, kp, oP);
+                        oQ = axpy(-P.ko_c, kq, oQ);
+                    }
+                }
+                if (P.gw != nullptr && i == P.i_ext) oP = c_add(oP, P.gw[r3]);
+                P.out_phi[static_cast<size_t>(r3) * ld + i] = oP;
+                P.out_pi[static_cast<size_t>(r3) * ld + i] = oQ;
+            }
+        }
+    }
+    // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
+    if (P.dA_part != nullptr) {
+        double v = dA;
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
+        if (lane == 0) P.dA_part[item] = v;
+    }
+}
+
+// Sum the per-wave partials of one launch into acc[slot] (single wave, fixed order).
+__global__ void __launch_bounds__(64) reduce_partials_kernel(const double* __restrict__ part, int n,
+                                                             double* __restrict__ acc) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += 64) v += part[k];
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
+    if (threadIdx.x == 0) acc[0] += v;
+}
+
+// Add g (nth complex) into column i_ext of Phi (residual injection).
+__global__ void __launch_bounds__(64) inject_column_kernel(double2* __restrict__ phi, int ld, int nth, int col,
+                                                           const double2* __restrict__ g) {
+    for (int j = threadIdx.x; j < nth; j += 64) phi[static_cast<size_t>(j) * ld + col] = c_add(phi[static_cast<size_t>(j) * ld + col], g[j]);
+}
+
+// a += ga, b += gb on [nth][nr] dense inputs into [nth][ld] planes.
+__global__ void __launch_bounds__(256) add_planes_kernel(double2* __restrict__ a, double2* __restrict__ b,
+                                                         const double2* __restrict__ ga,
+                                                         const double2* __restrict__ gb, int nr, int nth, int ld) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nr || j >= nth) return;
+    const size_t o = static_cast<size_t>(j) * ld + i, d = static_cast<size_t>(j) * nr + i;
+    if (ga != nullptr) a[o] = c_add(a[o], ga[d]);
+    if (gb != nullptr) b[o] = c_add(b[o], gb[d]);
+}
+
+hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const double2* gb, int nr, int nth,
+                             int ld, hipStream_t stream) {
+    hipLaunchKernelGGL(add_planes_kernel, dim3((nr + 255) / 256, nth), dim3(256), 0, stream, a, b, ga, gb, nr,
+                       nth, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream) {
+    const int items = P.nstrips * P.nseg;
+    const dim3 grid((items + 3) / 4), block(256);
+    switch (seg) {
+        case 4: hipLaunchKernelGGL(lw_adjoint_kernel<4>, grid, block, 0, stream, P); break;
+        case 8: hipLaunchKernelGGL(lw_adjoint_kernel<8>, grid, block, 0, stream, P); break;
+        case 16: hipLaunchKernelGGL(lw_adjoint_kernel<16>, grid, block, 0, stream, P); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* part, int n, double* acc, hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, stream, part, n, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream) {
+    hipLaunchKernelGGL(inject_column_kernel, dim3(1), dim3(64), 0, stream, phi, ld, nth, col, g);
+    return hipGetLastError();
+}
+
+}  // namespace teuk

@@ -34,6 +34,7 @@ int hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 constexpr int kSourceBatch = 256;   // iterations of source windows per compact pass
+constexpr int kPartSteps = 64;      // adjoint iterations whose dL/dA partials are reduced together
 
 }  // namespace
 
@@ -61,6 +62,15 @@ struct teuk_ctx {
     int4* d_org = nullptr;
     int64_t batch_n0 = -1;
     int batch_len = 0;
+    double batch_amp = 0.0;
+    // adjoint
+    double2* adj[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int adj_cur = 0;
+    int64_t adj_clock = -1;
+    double* d_dA = nullptr;        // accumulated dL/dA (device)
+    double* d_dA_part = nullptr;   // per-wave partials of up to kPartSteps iterations
+    int part_items = 0;            // partials per iteration (waves of the adjoint launch)
+    int part_filled = 0;           // iterations written since the last reduction
     // kernel timing (measurement aid)
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -108,8 +118,21 @@ void destroy_events(teuk_ctx* c) {
 
 constexpr size_t kTimingPool = 2048;
 
+void free_adjoint(teuk_ctx* c) {
+    for (auto& lv : c->adj)
+        for (auto& p : lv) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    (void)hipFree(c->d_dA);
+    (void)hipFree(c->d_dA_part);
+    c->d_dA = c->d_dA_part = nullptr;
+    c->adj_clock = -1;
+}
+
 void free_all(teuk_ctx* c) {
     destroy_events(c);
+    free_adjoint(c);
     free_source(c);
     for (auto& lv : c->plane)
         for (auto& p : lv) {
@@ -124,6 +147,51 @@ void free_all(teuk_ctx* c) {
 
 int check_ctx(const teuk_ctx* c) {
     if (c == nullptr) return fail(TEUK_EINVAL, "null context");
+    return TEUK_OK;
+}
+
+// Make the source windows of iteration n resident and return their slot.
+// Forward stepping fills [n, n + nb); the reverse sweep fills [n - nb + 1, n].
+int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t span, size_t* slot) {
+    if (!(n >= c->batch_n0 && n < c->batch_n0 + c->batch_len && amp == c->batch_amp)) {
+        const int nb = static_cast<int>(span < kSourceBatch ? span : kSourceBatch);
+        const int64_t n0 = backward ? n - nb + 1 : n;
+        const Geometry& G = c->G;
+        teuk::SourceParams S;
+        S.n0 = static_cast<int>(n0);
+        S.org = c->d_org;
+        S.win_r = c->win_r;
+        S.win_t = c->win_t;
+        S.orbit = c->d_orbit;
+        S.amplitude = amp;
+        S.sig_r = c->sig_r;
+        S.sig_th = c->sig_th;
+        S.cut = c->cut;
+        S.rs_min = G.rs_min;
+        S.h_r = G.h_r;
+        S.h_th = G.h_th;
+        S.m = G.m;
+        S.nr = G.nr;
+        S.nth = G.nth;
+        S.rnode_rs = c->d_rnode + static_cast<size_t>(teuk::RF_RS) * G.nr;
+        S.rhalf_rs = c->d_rhalf + static_cast<size_t>(teuk::RF_RS) * G.nr;
+        S.rows = c->d_rows;
+        S.fh = c->d_fh;
+        S.fn = c->d_fn;
+        HIP_TRY(teuk::launch_source_pass(S, nb, c->stream), "source pass");
+        c->batch_n0 = n0;
+        c->batch_len = nb;
+        c->batch_amp = amp;
+    }
+    *slot = static_cast<size_t>(n - c->batch_n0);
+    return TEUK_OK;
+}
+
+int flush_partials(teuk_ctx* c) {
+    if (c->part_filled == 0) return TEUK_OK;
+    HIP_TRY(teuk::launch_reduce_partials(c->d_dA_part, c->part_items * c->part_filled, c->d_dA, c->stream),
+            "dA reduction");
+    c->part_filled = 0;
     return TEUK_OK;
 }
 
@@ -313,8 +381,6 @@ int teuk_set_amplitude(teuk_ctx* c, double amplitude) {
     if (int rc = check_ctx(c)) return rc;
     if (!c->has_src) return fail(TEUK_ESTATE, "no source attached");
     c->amplitude = amplitude;
-    c->batch_n0 = -1;   // windows must be recomputed
-    c->batch_len = 0;
     return TEUK_OK;
 }
 
@@ -348,35 +414,8 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
         P.fh = P.fn = nullptr;
         P.org = nullptr;
         if (c->has_src) {
-            if (!(n >= c->batch_n0 && n < c->batch_n0 + c->batch_len)) {
-                const int64_t left = nsteps - k;
-                const int nb = static_cast<int>(left < kSourceBatch ? left : kSourceBatch);
-                teuk::SourceParams S;
-                S.n0 = static_cast<int>(n);
-                S.org = c->d_org;
-                S.win_r = c->win_r;
-                S.win_t = c->win_t;
-                S.orbit = c->d_orbit;
-                S.amplitude = c->amplitude;
-                S.sig_r = c->sig_r;
-                S.sig_th = c->sig_th;
-                S.cut = c->cut;
-                S.rs_min = G.rs_min;
-                S.h_r = G.h_r;
-                S.h_th = G.h_th;
-                S.m = G.m;
-                S.nr = G.nr;
-                S.nth = G.nth;
-                S.rnode_rs = c->d_rnode + static_cast<size_t>(teuk::RF_RS) * G.nr;
-                S.rhalf_rs = c->d_rhalf + static_cast<size_t>(teuk::RF_RS) * G.nr;
-                S.rows = c->d_rows;
-                S.fh = c->d_fh;
-                S.fn = c->d_fn;
-                HIP_TRY(teuk::launch_source_pass(S, nb, c->stream), "source pass");
-                c->batch_n0 = n;
-                c->batch_len = nb;
-            }
-            const size_t slot = static_cast<size_t>(n - c->batch_n0);
+            size_t slot = 0;
+            if (int rc = ensure_source(c, n, c->amplitude, false, nsteps - k, &slot)) return rc;
             const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
@@ -405,6 +444,135 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
         }
         c->cur ^= 1;
         c->steps_done += 1;
+    }
+    return TEUK_OK;
+}
+
+int teuk_adjoint_begin(teuk_ctx* c, const void* lam_phi, const void* lam_pi, int64_t n_end, const void* gw) {
+    if (int rc = check_ctx(c)) return rc;
+    if (n_end < 0) return fail(TEUK_EINVAL, "negative n_end");
+    const Geometry& G = c->G;
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
+    if (c->adj[0][0] == nullptr) {
+        const int max_items = c->nstrips * ((G.nth - 3) / 4 + 1);
+        hipError_t e = hipSuccess;
+        for (auto& lv : c->adj)
+            for (auto& p : lv)
+                if (e == hipSuccess) e = hipMalloc(&p, plane_bytes);
+        if (e == hipSuccess) e = hipMalloc(&c->d_dA, sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&c->d_dA_part, sizeof(double) * max_items * kPartSteps);
+        if (e != hipSuccess) {
+            free_adjoint(c);
+            return fail(TEUK_ENOMEM, std::string("adjoint buffers: ") + hipGetErrorString(e));
+        }
+    }
+    c->adj_cur = 0;
+    double2* P0 = c->adj[0][0];
+    double2* P1 = c->adj[0][1];
+    const size_t w = sizeof(double2) * G.nr;
+    if (lam_phi != nullptr) {
+        HIP_TRY(hipMemcpy2DAsync(P0, sizeof(double2) * c->ld, lam_phi, w, w, G.nth, hipMemcpyDeviceToDevice,
+                                 c->stream), "adjoint_begin copy");
+    } else {
+        HIP_TRY(hipMemsetAsync(P0, 0, plane_bytes, c->stream), "adjoint_begin zero");
+    }
+    if (lam_pi != nullptr) {
+        HIP_TRY(hipMemcpy2DAsync(P1, sizeof(double2) * c->ld, lam_pi, w, w, G.nth, hipMemcpyDeviceToDevice,
+                                 c->stream), "adjoint_begin copy");
+    } else {
+        HIP_TRY(hipMemsetAsync(P1, 0, plane_bytes, c->stream), "adjoint_begin zero");
+    }
+    if (gw != nullptr && n_end >= 1)
+        HIP_TRY(teuk::launch_inject_column(P0, c->ld, G.nth, G.i_ext,
+                                           static_cast<const double2*>(gw) + (n_end - 1) * G.nth, c->stream),
+                "adjoint_begin inject");
+    HIP_TRY(hipMemsetAsync(c->d_dA, 0, sizeof(double), c->stream), "dA zero");
+    c->part_filled = 0;
+    c->adj_clock = n_end;
+    return TEUK_OK;
+}
+
+int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
+    if (int rc = check_ctx(c)) return rc;
+    if (c->adj_clock < 0) return fail(TEUK_ESTATE, "teuk_adjoint_begin first");
+    if (nsteps < 0 || nsteps > c->adj_clock) return fail(TEUK_EINVAL, "step count beyond iteration 0");
+    const Geometry& G = c->G;
+    if (c->has_src && 2 * (c->adj_clock - 1) + 1 >= c->nsamples && nsteps > 0)
+        return fail(TEUK_ESTATE, "orbit has too few samples for the reverse sweep");
+    teuk::AdjointParams P;
+    P.rnode = c->d_rnode;
+    P.rhalf = c->d_rhalf;
+    P.rows = c->d_rows;
+    P.nr = G.nr;
+    P.nth = G.nth;
+    P.ld = c->ld;
+    P.rpitch = G.nr;
+    P.nstrips = c->nstrips;
+    P.nseg = c->nseg;
+    P.dt = G.dt;
+    P.inv_hr = 1.0 / G.h_r;
+    P.ko_c = c->ko_c;
+    P.even = (std::abs(G.m) % 2 == 0);
+    P.i_ext = G.i_ext;
+    P.win_r = c->win_r;
+    P.win_t = c->win_t;
+    const int items = c->nstrips * c->nseg;
+    if (c->part_items != items) {
+        if (int rc = flush_partials(c)) return rc;
+        c->part_items = items;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t m = c->adj_clock - 1;
+        P.fh = P.fn = nullptr;
+        P.org = nullptr;
+        P.dA_part = nullptr;
+        if (c->has_src) {
+            size_t slot = 0;
+            if (int rc = ensure_source(c, m, 1.0, true, m + 1, &slot)) return rc;
+            const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
+            P.fh = c->d_fh + slot * wsz;
+            P.fn = c->d_fn + slot * wsz;
+            P.org = c->d_org + slot;
+            if (c->part_filled == kPartSteps)
+                if (int rc = flush_partials(c)) return rc;
+            P.dA_part = c->d_dA_part + static_cast<size_t>(c->part_filled) * items;
+            c->part_filled += 1;
+        }
+        P.gw = (gw != nullptr && m >= 1) ? static_cast<const double2*>(gw) + (m - 1) * G.nth : nullptr;
+        P.lam_phi = c->adj[c->adj_cur][0];
+        P.lam_pi = c->adj[c->adj_cur][1];
+        P.out_phi = c->adj[c->adj_cur ^ 1][0];
+        P.out_pi = c->adj[c->adj_cur ^ 1][1];
+        HIP_TRY(teuk::launch_adjoint(P, c->seg_rows, c->stream), "adjoint kernel");
+        c->adj_cur ^= 1;
+        c->adj_clock = m;
+    }
+    return TEUK_OK;
+}
+
+int teuk_adjoint_add_state(teuk_ctx* c, const void* gphi, const void* gpi) {
+    if (int rc = check_ctx(c)) return rc;
+    if (c->adj_clock < 0) return fail(TEUK_ESTATE, "teuk_adjoint_begin first");
+    HIP_TRY(teuk::launch_add_planes(c->adj[c->adj_cur][0], c->adj[c->adj_cur][1],
+                                    static_cast<const double2*>(gphi), static_cast<const double2*>(gpi),
+                                    c->G.nr, c->G.nth, c->ld, c->stream), "adjoint_add_state");
+    return TEUK_OK;
+}
+
+int teuk_adjoint_get(teuk_ctx* c, void* lam_phi, void* lam_pi, double* dL_dA) {
+    if (int rc = check_ctx(c)) return rc;
+    if (c->adj_clock < 0) return fail(TEUK_ESTATE, "teuk_adjoint_begin first");
+    const size_t w = sizeof(double2) * c->G.nr;
+    if (lam_phi != nullptr)
+        HIP_TRY(hipMemcpy2DAsync(lam_phi, w, c->adj[c->adj_cur][0], sizeof(double2) * c->ld, w, c->G.nth,
+                                 hipMemcpyDeviceToDevice, c->stream), "adjoint_get");
+    if (lam_pi != nullptr)
+        HIP_TRY(hipMemcpy2DAsync(lam_pi, w, c->adj[c->adj_cur][1], sizeof(double2) * c->ld, w, c->G.nth,
+                                 hipMemcpyDeviceToDevice, c->stream), "adjoint_get");
+    if (dL_dA != nullptr) {
+        if (int rc = flush_partials(c)) return rc;
+        HIP_TRY(hipMemcpyAsync(dL_dA, c->d_dA, sizeof(double), hipMemcpyDeviceToHost, c->stream), "dA copy");
+        HIP_TRY(hipStreamSynchronize(c->stream), "adjoint_get sync");
     }
     return TEUK_OK;
 }

@@ -57,7 +57,33 @@ struct PulseParams {
     int even;
 };
 
+struct AdjointParams {
+    const double2* lam_phi;     // lambda^{n+1} planes [nth][ld]
+    const double2* lam_pi;
+    double2* out_phi;           // lambda^n planes
+    double2* out_pi;
+    const double* rnode;
+    const double* rhalf;
+    const ThetaRow* rows;
+    int nr, nth, ld, rpitch;
+    int nstrips, nseg;
+    double dt, inv_hr, ko_c;
+    int even;
+    int i_ext;
+    const double2* gw;          // dL/dw_n to inject at column i_ext after the step (nth), or null
+    const double2* fh;          // unit-amplitude source windows of the forward iteration n
+    const double2* fn;
+    const int4* org;
+    int win_r, win_t;
+    double* dA_part;            // one partial of dL/dA per wave (nstrips * nseg), or null
+};
+
 bool valid_segment_rows(int seg);
+hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream);
+hipError_t launch_reduce_partials(const double* part, int n, double* acc, hipStream_t stream);
+hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream);
+hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const double2* gb, int nr, int nth,
+                             int ld, hipStream_t stream);
 hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);
 hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream);

@@ -47,6 +47,11 @@ class Engine:
         self.ctx = ctx
         self.m = int(m)
         self._orbit = None
+        self._gw = None
+
+    @property
+    def has_source(self):
+        return self._orbit is not None
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -143,6 +148,39 @@ class Engine:
     def set_tuning(self, seg_rows):
         t = L.Tuning(int(seg_rows))
         L.check(self._lib.teuk_set_tuning(self.ctx, ctypes.byref(t)))
+
+    # -- adjoint ------------------------------------------------------------
+    def adjoint_begin(self, n_end, lam_phi=None, lam_pi=None, gw=None):
+        """lambda := (lam_phi, lam_pi) (None = 0) + dL/dw_{n_end}; clock := n_end."""
+        shape = self.shape
+        for t, name in ((lam_phi, "lam_phi"), (lam_pi, "lam_pi")):
+            if t is not None:
+                _need_device(t, shape, name)
+        if gw is not None:
+            _need_device(gw, (gw.shape[0], shape[0]), "gw")
+            if gw.shape[0] < int(n_end):
+                raise ValueError("gw needs a row for every forward iteration 1..n_end")
+        self._gw = gw
+        L.check(self._lib.teuk_adjoint_begin(self.ctx, _ptr(lam_phi) if lam_phi is not None else None,
+                                             _ptr(lam_pi) if lam_pi is not None else None, int(n_end),
+                                             _ptr(gw) if gw is not None else None))
+
+    def adjoint_step(self, nsteps, gw=None):
+        gw = gw if gw is not None else self._gw
+        L.check(self._lib.teuk_adjoint_step_n(self.ctx, int(nsteps), _ptr(gw) if gw is not None else None))
+
+    def adjoint_add_state(self, gphi=None, gpi=None):
+        L.check(self._lib.teuk_adjoint_add_state(self.ctx, _ptr(gphi) if gphi is not None else None,
+                                                 _ptr(gpi) if gpi is not None else None))
+
+    def adjoint_get(self, want_dA=True):
+        """(lambda_phi, lambda_pi, dL/dA or None)."""
+        nth, nr = self.shape
+        p = torch.empty((nth, nr), dtype=torch.complex128, device="cuda")
+        q = torch.empty_like(p)
+        dA = ctypes.c_double(0.0)
+        L.check(self._lib.teuk_adjoint_get(self.ctx, _ptr(p), _ptr(q), ctypes.byref(dA) if want_dA else None))
+        return p, q, (dA.value if want_dA else None)
 
     def set_kernel_timing(self, enable):
         L.check(self._lib.teuk_set_kernel_timing(self.ctx, 1 if enable else 0))
