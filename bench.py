@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
     ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -90,6 +91,54 @@ def make_engine(cfg, nsteps):
 def run_evolution(eng, zero_phi, zero_pi, nsteps, wave):
     eng.set_state(zero_phi, zero_pi)
     eng.step(nsteps, out=wave)
+
+
+def adjoint_ratio(args):
+    """Adjoint/forward time ratio on the 3200 x 64 adjoint workload (20000
+    iterations): forward with extraction; reverse sweep driven by the
+    waveform residual (no states needed); and the checkpointed pair
+    (snapshots every ceil(sqrt(N)) iterations, every segment recomputed)."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    cfg = W.ADJOINT
+    g = cfg["grid"]
+    n = cfg["steps"]
+    eng = make_engine(cfg, n)
+    y = torch.zeros((n, g["nth"]), dtype=torch.complex128, device="cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, out
+
+    def fwd():
+        eng.init_pulse(**cfg["pulse"])
+        return eng.step(n)
+
+    fwd()                                                   # warm-up
+    tf, w = timed(fwd)
+    gw = (2.0 * (w - y)).contiguous()
+
+    def adj():
+        eng.adjoint_begin(n, gw=gw)
+        eng.adjoint_step(n)
+        return eng.adjoint_get()
+
+    adj()
+    ta, _ = timed(adj)
+
+    def ckpt():
+        eng.init_pulse(**cfg["pulse"])
+        eng.forward_checkpointed(n, interval=0, force_recompute=True)
+        return eng.backward_checkpointed(gw, 0.0)
+
+    tc, _ = timed(ckpt)
+    eng.close()
+    return {"workload": cfg["name"], "iterations": n, "forward_s": round(tf, 4), "adjoint_s": round(ta, 4),
+            "ratio": round(ta / tf, 3), "forward_plus_backward_with_recompute_s": round(tc, 4),
+            "ratio_with_recompute": round((tc - tf) / tf, 3)}
 
 
 def cpu_baseline(cfg, iters):
@@ -188,6 +237,10 @@ def main():
                              "kernel_frac_of_peak": round(hpts * BYTES_PER_POINT / havg / 1e9 / HBM_PEAK_GBS, 4)}
         print(f"[bench] {hc['name']}: {extra['hbm_grid']}", file=sys.stderr, flush=True)
         heng.close()
+
+    if not args.no_adjoint:
+        extra["adjoint"] = adjoint_ratio(args)
+        print(f"[bench] adjoint: {extra['adjoint']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

@@ -168,6 +168,41 @@ int teuk_adjoint_step_n(teuk_ctx* ctx, int64_t nsteps, const void* gw_dev);
 int teuk_adjoint_add_state(teuk_ctx* ctx, const void* gphi_dev, const void* gpi_dev);
 int teuk_adjoint_get(teuk_ctx* ctx, void* lam_phi_dev, void* lam_pi_dev, double* dL_dA);
 
+/* ---- Checkpointed gradient -----------------------------------------------
+ * A loss may depend on states the caller does not keep:
+ *   L_s = state_weight * sum_{n = n_lo..n_hi} sum_{j0 <= j < j1, i0 <= i < i1} |Phi^n_ij|^2.
+ * Its reverse sweep needs Phi^n at every n in [n_lo, n_hi], so the forward
+ * keeps one snapshot of (Phi, Pi) every `interval` iterations (0 picks
+ * ceil(sqrt(nsteps))) and the backward recomputes each segment from its
+ * snapshot before sweeping it in reverse (memory: nsteps/interval
+ * snapshots plus one segment of the rectangle).  With state_weight = 0 the
+ * states are not needed; force_recompute != 0 recomputes the segments
+ * anyway (same gradient, bitwise).
+ *
+ * teuk_forward_checkpointed: from the state set by teuk_set_state or
+ *   teuk_init_pulse (no iteration taken since), runs plan->nsteps
+ *   iterations, writing the waveform (device, may be NULL) as teuk_step_n
+ *   does, and, if state_loss is not NULL, stores L_s there (host;
+ *   synchronizes).
+ * teuk_backward_checkpointed: right after the forward with the same plan,
+ *   takes dL/dw (gw_dev, forward waveform layout, may be NULL) and dL/dL_s,
+ *   and writes dL/dPhi^0, dL/dPi^0 (device [nth][nr]) and dL/dA (host, may
+ *   be NULL; synchronizes).  The forward state is left at an intermediate
+ *   iteration afterwards. */
+typedef struct {
+    int64_t nsteps;
+    int64_t interval;
+    double state_weight;
+    int32_t i0, i1, j0, j1;
+    int64_t n_lo, n_hi;
+    int32_t force_recompute;
+} teuk_grad_plan;
+
+int teuk_forward_checkpointed(teuk_ctx* ctx, const teuk_grad_plan* plan, void* waveform_dev,
+                              double* state_loss);
+int teuk_backward_checkpointed(teuk_ctx* ctx, const teuk_grad_plan* plan, const void* gw_dev,
+                               double dL_dLs, void* grad_phi0_dev, void* grad_pi0_dev, double* dL_dA);
+
 /* Current Phi column at the extraction radius: nth complex128 (device). */
 int teuk_extract_waveform(const teuk_ctx* ctx, void* out_dev);
 

@@ -54,6 +54,13 @@ class SourceDesc(ctypes.Structure):
                 ("nsamples", ctypes.c_int64), ("orbit", ctypes.POINTER(ctypes.c_double))]
 
 
+class GradPlan(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_int64), ("interval", ctypes.c_int64),
+                ("state_weight", ctypes.c_double),
+                ("i0", ctypes.c_int32), ("i1", ctypes.c_int32), ("j0", ctypes.c_int32), ("j1", ctypes.c_int32),
+                ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64), ("force_recompute", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _CTX = ctypes.c_void_p
 
@@ -72,6 +79,10 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_double)]),
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
+    "teuk_forward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P,
+                                                 ctypes.POINTER(ctypes.c_double)]),
+    "teuk_backward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P, ctypes.c_double, _P, _P,
+                                                  ctypes.POINTER(ctypes.c_double)]),
     "teuk_adjoint_begin": (ctypes.c_int, [_CTX, _P, _P, ctypes.c_int64, _P]),
     "teuk_adjoint_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_adjoint_add_state": (ctypes.c_int, [_CTX, _P, _P]),

@@ -45,3 +45,31 @@ class TeukEvolve(torch.autograd.Function):
 def evolve(phi0, pi0, amplitude, engine, nsteps):
     """Differentiable evolution; see TeukEvolve."""
     return TeukEvolve.apply(phi0, pi0, amplitude, engine, nsteps)
+
+
+class TeukEvolveCheckpointed(torch.autograd.Function):
+    """(w, L_s) = TeukEvolveCheckpointed.apply(phi0, pi0, amplitude, engine, nsteps, state_loss, interval).
+
+    Like TeukEvolve, plus the state loss
+    L_s = weight * sum_{n=n_lo..n_hi} sum_rect |Phi^n|^2 (state_loss dict), whose
+    gradient needs the intermediate states: the forward keeps a snapshot every
+    `interval` iterations (0 = ceil(sqrt(nsteps))) and the backward recomputes
+    each segment before sweeping it in reverse."""
+
+    @staticmethod
+    def forward(ctx, phi0, pi0, amplitude, engine, nsteps, state_loss, interval=0):
+        engine.set_state(phi0.detach().contiguous(), pi0.detach().contiguous())
+        if engine.has_source:
+            engine.set_amplitude(float(amplitude))
+        w, ls = engine.forward_checkpointed(int(nsteps), interval, state_loss)
+        ctx.engine = engine
+        return w, torch.tensor(ls, dtype=torch.float64, device=w.device)
+
+    @staticmethod
+    def backward(ctx, gw, gls):
+        eng = ctx.engine
+        gw = gw.detach().contiguous() if gw is not None else None
+        dls = float(gls) if gls is not None else 0.0
+        gp, gq, dA = eng.backward_checkpointed(gw, dls)
+        gA = torch.tensor(dA, dtype=torch.float64, device=gp.device)
+        return gp, gq, gA, None, None, None, None

@@ -327,3 +327,59 @@ hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const do
 }
 
 }  // namespace teuk
+
+namespace teuk {
+
+// ---------------------------------------------------------------------------
+// Helpers of the checkpointed gradient: a loss on a rectangle of Phi and the
+// injection of its gradient.
+// ---------------------------------------------------------------------------
+
+// part[row - j0] = sum_{i0 <= i < i1} |Phi(row, i)|^2 (one block per row, fixed order).
+__global__ void __launch_bounds__(256) region_sumsq_kernel(const double2* __restrict__ phi, int ld, int i0,
+                                                           int i1, int j0, double* __restrict__ part) {
+    __shared__ double red[256];
+    const int j = j0 + blockIdx.x;
+    double v = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double2 u = phi[static_cast<size_t>(j) * ld + i];
+        v = fma(u.x, u.x, fma(u.y, u.y, v));
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// lam(row, i) += scale * src(row, i) over the rectangle; src is either a
+// plane with pitch src_ld at the same coordinates, or a dense region buffer
+// (src_ld = i1 - i0, origin (j0, i0) subtracted).
+__global__ void __launch_bounds__(256) add_region_kernel(double2* __restrict__ lam, int ld,
+                                                         const double2* __restrict__ src, int src_ld,
+                                                         bool dense, double scale, int i0, int i1, int j0) {
+    const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = j0 + blockIdx.y;
+    if (i >= i1) return;
+    const double2 s = dense ? src[static_cast<size_t>(blockIdx.y) * src_ld + (i - i0)]
+                            : src[static_cast<size_t>(j) * src_ld + i];
+    double2& l = lam[static_cast<size_t>(j) * ld + i];
+    l = make_double2(fma(scale, s.x, l.x), fma(scale, s.y, l.y));
+}
+
+hipError_t launch_region_sumsq(const double2* phi, int ld, int i0, int i1, int j0, int j1, double* part,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(region_sumsq_kernel, dim3(j1 - j0), dim3(256), 0, stream, phi, ld, i0, i1, j0, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_region(double2* lam, int ld, const double2* src, int src_ld, bool dense, double scale,
+                             int i0, int i1, int j0, int j1, hipStream_t stream) {
+    hipLaunchKernelGGL(add_region_kernel, dim3((i1 - i0 + 255) / 256, j1 - j0), dim3(256), 0, stream, lam, ld,
+                       src, src_ld, dense, scale, i0, i1, j0);
+    return hipGetLastError();
+}
+
+}  // namespace teuk

@@ -1,6 +1,7 @@
 // C ABI of the engine (declared in include/teuk.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -71,6 +72,14 @@ struct teuk_ctx {
     double* d_dA_part = nullptr;   // per-wave partials of up to kPartSteps iterations
     int part_items = 0;            // partials per iteration (waves of the adjoint launch)
     int part_filled = 0;           // iterations written since the last reduction
+    // checkpointed gradient
+    std::vector<double2*> snaps;   // 2 planes per snapshot: [2k] Phi, [2k+1] Pi
+    double2* seg_buf = nullptr;    // Phi on the loss rectangle, one slot per segment iteration
+    size_t seg_buf_bytes = 0;
+    double* d_ls = nullptr;        // accumulated sum |Phi|^2 over the rectangle
+    double* d_ls_part = nullptr;   // per-row partials (nth)
+    bool ckpt_valid = false;
+    teuk_grad_plan ckpt_plan{};
     // kernel timing (measurement aid)
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -130,8 +139,21 @@ void free_adjoint(teuk_ctx* c) {
     c->adj_clock = -1;
 }
 
+void free_ckpt(teuk_ctx* c) {
+    for (auto p : c->snaps) (void)hipFree(p);
+    c->snaps.clear();
+    (void)hipFree(c->seg_buf);
+    (void)hipFree(c->d_ls);
+    (void)hipFree(c->d_ls_part);
+    c->seg_buf = nullptr;
+    c->seg_buf_bytes = 0;
+    c->d_ls = c->d_ls_part = nullptr;
+    c->ckpt_valid = false;
+}
+
 void free_all(teuk_ctx* c) {
     destroy_events(c);
+    free_ckpt(c);
     free_adjoint(c);
     free_source(c);
     for (auto& lv : c->plane)
@@ -415,7 +437,10 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
         P.org = nullptr;
         if (c->has_src) {
             size_t slot = 0;
-            if (int rc = ensure_source(c, n, c->amplitude, false, nsteps - k, &slot)) return rc;
+            // a batch may run past this call, as far as the orbit has samples:
+            // the last iteration it supports is (nsamples - 2) / 2 (needs sample 2n + 1)
+            const int64_t span = (c->nsamples - 2) / 2 - n + 1;
+            if (int rc = ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
             const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
@@ -575,6 +600,145 @@ int teuk_adjoint_get(teuk_ctx* c, void* lam_phi, void* lam_pi, double* dL_dA) {
         HIP_TRY(hipStreamSynchronize(c->stream), "adjoint_get sync");
     }
     return TEUK_OK;
+}
+
+static int check_plan(const teuk_ctx* c, const teuk_grad_plan* p, int64_t* interval) {
+    if (p == nullptr) return fail(TEUK_EINVAL, "null plan");
+    if (p->nsteps < 1) return fail(TEUK_EINVAL, "plan needs nsteps >= 1");
+    int64_t iv = p->interval;
+    if (iv == 0) iv = static_cast<int64_t>(std::ceil(std::sqrt(static_cast<double>(p->nsteps))));
+    if (iv < 1) return fail(TEUK_EINVAL, "interval must be >= 0");
+    if (p->state_weight != 0.0) {
+        if (!(0 <= p->i0 && p->i0 < p->i1 && p->i1 <= c->G.nr && 0 <= p->j0 && p->j0 < p->j1 &&
+              p->j1 <= c->G.nth))
+            return fail(TEUK_EINVAL, "loss rectangle outside the grid");
+        if (!(1 <= p->n_lo && p->n_lo <= p->n_hi && p->n_hi <= p->nsteps))
+            return fail(TEUK_EINVAL, "need 1 <= n_lo <= n_hi <= nsteps");
+    }
+    *interval = iv;
+    return TEUK_OK;
+}
+
+int teuk_forward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, void* waveform, double* state_loss) {
+    if (int rc = check_ctx(c)) return rc;
+    int64_t iv = 0;
+    if (int rc = check_plan(c, plan, &iv)) return rc;
+    if (c->steps_done != 0) return fail(TEUK_ESTATE, "set the initial state first (no iteration taken since)");
+    const Geometry& G = c->G;
+    const int64_t N = plan->nsteps;
+    const int64_t K = (N + iv - 1) / iv;
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
+    c->ckpt_valid = false;
+    while (static_cast<int64_t>(c->snaps.size()) < 2 * K) {
+        double2* p = nullptr;
+        hipError_t e = hipMalloc(&p, plane_bytes);
+        if (e != hipSuccess) return fail(TEUK_ENOMEM, std::string("checkpoint snapshots: ") + hipGetErrorString(e));
+        c->snaps.push_back(p);
+    }
+    const bool sl = plan->state_weight != 0.0;
+    if (sl && c->d_ls == nullptr) {
+        hipError_t e = hipMalloc(&c->d_ls, sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&c->d_ls_part, sizeof(double) * G.nth);
+        if (e != hipSuccess) return fail(TEUK_ENOMEM, "state-loss buffers");
+    }
+    if (sl) HIP_TRY(hipMemsetAsync(c->d_ls, 0, sizeof(double), c->stream), "state loss zero");
+    double2* wave = static_cast<double2*>(waveform);
+    for (int64_t k = 0; k < K; ++k) {
+        const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
+        HIP_TRY(hipMemcpyAsync(c->snaps[2 * k], c->plane[c->cur][0], plane_bytes, hipMemcpyDeviceToDevice,
+                               c->stream), "snapshot");
+        HIP_TRY(hipMemcpyAsync(c->snaps[2 * k + 1], c->plane[c->cur][1], plane_bytes, hipMemcpyDeviceToDevice,
+                               c->stream), "snapshot");
+        const bool touches = sl && !(s1 < plan->n_lo || s0 + 1 > plan->n_hi);
+        if (!touches) {
+            if (int rc = teuk_step_n(c, s1 - s0, wave ? wave + s0 * G.nth : nullptr)) return rc;
+            continue;
+        }
+        for (int64_t n = s0; n < s1; ++n) {
+            if (int rc = teuk_step_n(c, 1, wave ? wave + n * G.nth : nullptr)) return rc;
+            if (n + 1 >= plan->n_lo && n + 1 <= plan->n_hi) {
+                HIP_TRY(teuk::launch_region_sumsq(c->plane[c->cur][0], c->ld, plan->i0, plan->i1, plan->j0,
+                                                  plan->j1, c->d_ls_part, c->stream), "state loss");
+                HIP_TRY(teuk::launch_reduce_partials(c->d_ls_part, plan->j1 - plan->j0, c->d_ls, c->stream),
+                        "state loss reduction");
+            }
+        }
+    }
+    if (state_loss != nullptr) {
+        double acc = 0.0;
+        if (sl) {
+            HIP_TRY(hipMemcpyAsync(&acc, c->d_ls, sizeof(double), hipMemcpyDeviceToHost, c->stream), "loss copy");
+            HIP_TRY(hipStreamSynchronize(c->stream), "loss sync");
+        }
+        *state_loss = plan->state_weight * acc;
+    }
+    c->ckpt_plan = *plan;
+    c->ckpt_valid = true;
+    return TEUK_OK;
+}
+
+int teuk_backward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, const void* gw, double dL_dLs,
+                               void* grad_phi0, void* grad_pi0, double* dL_dA) {
+    if (int rc = check_ctx(c)) return rc;
+    int64_t iv = 0;
+    if (int rc = check_plan(c, plan, &iv)) return rc;
+    if (!c->ckpt_valid || std::memcmp(&c->ckpt_plan, plan, sizeof(teuk_grad_plan)) != 0 ||
+        c->steps_done != plan->nsteps)
+        return fail(TEUK_ESTATE, "run teuk_forward_checkpointed with the same plan first");
+    const Geometry& G = c->G;
+    const int64_t N = plan->nsteps;
+    const int64_t K = (N + iv - 1) / iv;
+    const bool sl = plan->state_weight != 0.0;
+    const bool recompute = sl || plan->force_recompute != 0;
+    const double scale = 2.0 * plan->state_weight * dL_dLs;
+    const int wr = plan->i1 - plan->i0, hr = plan->j1 - plan->j0;
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
+    if (sl) {
+        const size_t need = sizeof(double2) * static_cast<size_t>(wr) * hr * iv;
+        if (c->seg_buf_bytes < need) {
+            (void)hipFree(c->seg_buf);
+            c->seg_buf = nullptr;
+            c->seg_buf_bytes = 0;
+            hipError_t e = hipMalloc(&c->seg_buf, need);
+            if (e != hipSuccess) return fail(TEUK_ENOMEM, "segment buffer");
+            c->seg_buf_bytes = need;
+        }
+    }
+    if (int rc = teuk_adjoint_begin(c, nullptr, nullptr, N, gw)) return rc;
+    if (sl && N >= plan->n_lo && N <= plan->n_hi)
+        HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld, c->plane[c->cur][0], c->ld, false, scale,
+                                        plan->i0, plan->i1, plan->j0, plan->j1, c->stream), "state grad");
+    for (int64_t k = K - 1; k >= 0; --k) {
+        const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
+        if (recompute) {
+            // restore u^{s0} and recompute the segment, keeping Phi on the rectangle
+            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][0], c->snaps[2 * k], plane_bytes, hipMemcpyDeviceToDevice,
+                                   c->stream), "restore");
+            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][1], c->snaps[2 * k + 1], plane_bytes,
+                                   hipMemcpyDeviceToDevice, c->stream), "restore");
+            c->steps_done = s0;
+            for (int64_t m = s0; m < s1; ++m) {
+                if (sl && m >= plan->n_lo && m <= plan->n_hi)
+                    HIP_TRY(hipMemcpy2DAsync(c->seg_buf + static_cast<size_t>(m - s0) * wr * hr,
+                                             sizeof(double2) * wr,
+                                             c->plane[c->cur][0] + static_cast<size_t>(plan->j0) * c->ld + plan->i0,
+                                             sizeof(double2) * c->ld, sizeof(double2) * wr, hr,
+                                             hipMemcpyDeviceToDevice, c->stream), "segment store");
+                if (m + 1 < s1)
+                    if (int rc = teuk_step_n(c, 1, nullptr)) return rc;
+            }
+        }
+        for (int64_t m = s1 - 1; m >= s0; --m) {
+            if (int rc = teuk_adjoint_step_n(c, 1, gw)) return rc;
+            if (sl && m >= 1 && m >= plan->n_lo && m <= plan->n_hi)
+                HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld,
+                                                c->seg_buf + static_cast<size_t>(m - s0) * wr * hr, wr, true,
+                                                scale, plan->i0, plan->i1, plan->j0, plan->j1, c->stream),
+                        "state grad");
+        }
+    }
+    c->ckpt_valid = false;
+    return teuk_adjoint_get(c, grad_phi0, grad_pi0, dL_dA);
 }
 
 int teuk_extract_waveform(const teuk_ctx* c, void* out) {

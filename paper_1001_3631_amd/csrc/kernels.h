@@ -78,6 +78,11 @@ struct AdjointParams {
     double* dA_part;            // one partial of dL/dA per wave (nstrips * nseg), or null
 };
 
+hipError_t launch_region_sumsq(const double2* phi, int ld, int i0, int i1, int j0, int j1, double* part,
+                               hipStream_t stream);
+hipError_t launch_add_region(double2* lam, int ld, const double2* src, int src_ld, bool dense, double scale,
+                             int i0, int i1, int j0, int j1, hipStream_t stream);
+
 bool valid_segment_rows(int seg);
 hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream);
 hipError_t launch_reduce_partials(const double* part, int n, double* acc, hipStream_t stream);

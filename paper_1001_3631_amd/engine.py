@@ -182,6 +182,39 @@ class Engine:
         L.check(self._lib.teuk_adjoint_get(self.ctx, _ptr(p), _ptr(q), ctypes.byref(dA) if want_dA else None))
         return p, q, (dA.value if want_dA else None)
 
+    # -- checkpointed gradient ----------------------------------------------
+    def _plan(self, nsteps, interval, state_loss, force_recompute):
+        sl = state_loss or {}
+        return L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
+                          int(sl.get("i0", 0)), int(sl.get("i1", 0)), int(sl.get("j0", 0)),
+                          int(sl.get("j1", 0)), int(sl.get("n_lo", 0)), int(sl.get("n_hi", 0)),
+                          1 if force_recompute else 0)
+
+    def forward_checkpointed(self, nsteps, interval=0, state_loss=None, force_recompute=False):
+        """Run nsteps iterations keeping snapshots for the reverse sweep.
+        state_loss: dict(weight, i0, i1, j0, j1, n_lo, n_hi) for
+        L_s = weight * sum_{n=n_lo..n_hi} sum_rect |Phi^n|^2, or None.
+        Returns (waveform, L_s)."""
+        self._ckpt = self._plan(nsteps, interval, state_loss, force_recompute)
+        nth = self.shape[0]
+        w = torch.empty((int(nsteps), nth), dtype=torch.complex128, device="cuda")
+        ls = ctypes.c_double(0.0)
+        L.check(self._lib.teuk_forward_checkpointed(self.ctx, ctypes.byref(self._ckpt), _ptr(w), ctypes.byref(ls)))
+        return w, ls.value
+
+    def backward_checkpointed(self, gw=None, dL_dLs=1.0):
+        """Gradients (dL/dPhi0, dL/dPi0, dL/dA) after forward_checkpointed."""
+        nth, nr = self.shape
+        if gw is not None:
+            _need_device(gw, (self._ckpt.nsteps, nth), "gw")
+        gp = torch.empty((nth, nr), dtype=torch.complex128, device="cuda")
+        gq = torch.empty_like(gp)
+        dA = ctypes.c_double(0.0)
+        L.check(self._lib.teuk_backward_checkpointed(self.ctx, ctypes.byref(self._ckpt),
+                                                     _ptr(gw) if gw is not None else None, float(dL_dLs),
+                                                     _ptr(gp), _ptr(gq), ctypes.byref(dA)))
+        return gp, gq, dA.value
+
     def set_kernel_timing(self, enable):
         L.check(self._lib.teuk_set_kernel_timing(self.ctx, 1 if enable else 0))
 

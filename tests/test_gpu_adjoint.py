@@ -156,3 +156,187 @@ def test_autograd_function_gradients():
     gp, gq, gA = eng.adjoint_get()
     assert rel(host(P0.grad), host(gp)) <= 1e-13 and rel(host(Q0.grad), host(gq)) <= 1e-13
     assert abs(float(A.grad) - gA) <= 1e-13 * abs(gA)
+
+
+# ---------------------------------------------------------------------------
+# Checkpointed gradient (snapshots + recompute) for losses on the states
+# ---------------------------------------------------------------------------
+
+STATE_LOSS = dict(weight=0.7, i0=40, i1=121, j0=5, j1=21, n_lo=30, n_hi=100)
+
+
+def _masked(phi, sl):
+    out = np.zeros_like(phi)
+    out[sl["j0"]:sl["j1"], sl["i0"]:sl["i1"]] = phi[sl["j0"]:sl["j1"], sl["i0"]:sl["i1"]]
+    return out
+
+
+def test_checkpoint_recompute_equals_residual_only_bitwise():
+    grid, n = _adjoint_case()
+    g = T.Grid(**grid)
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    y = to_dev(W.target_noise((n, g.nth), 0.05, seed=4))
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    eng.set_state(to_dev(phi0), to_dev(pi0))
+    w = eng.step(n)
+    gw = (2.0 * (w - y)).contiguous()
+    eng.adjoint_begin(n, gw=gw)
+    eng.adjoint_step(n)
+    gp0, gq0, dA0 = eng.adjoint_get()
+    for interval in (0, 7, n):
+        eng.set_state(to_dev(phi0), to_dev(pi0))
+        w2, _ = eng.forward_checkpointed(n, interval=interval, force_recompute=True)
+        assert torch.equal(w2, w)
+        gp, gq, dA = eng.backward_checkpointed(gw)
+        assert torch.equal(gp, gp0) and torch.equal(gq, gq0) and dA == dA0
+
+
+def test_checkpointed_state_loss_gradient_matches_oracle():
+    grid, n = _adjoint_case()
+    g = T.Grid(**grid)
+    sl = STATE_LOSS
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    y = W.target_noise((n, g.nth), 0.05, seed=4)
+    src = oracle_source(g, SRC, n)
+    snaps = {k: None for k in range(sl["n_lo"], sl["n_hi"] + 1)}
+    w = T.evolve(g, phi0, pi0, n, src, snapshots=snaps)[2]
+    rls = sl["weight"] * sum(np.sum(np.abs(_masked(snaps[k][0], sl)) ** 2) for k in snaps)
+    _, gw = T.waveform_loss(w, y)
+    z = np.zeros_like(phi0)
+    sg = lambda k: (2 * sl["weight"] * _masked(snaps[k][0], sl), z) if k in snaps else None
+    rgp, rgq, rdA = T.adjoint_evolve(g, gw, n, src, state_grad=sg)
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    eng.set_state(to_dev(phi0), to_dev(pi0))
+    wg, ls = eng.forward_checkpointed(n, interval=0, state_loss=sl)
+    assert abs(ls - rls) <= 1e-12 * rls
+    gp, gq, dA = eng.backward_checkpointed((2.0 * (wg - to_dev(y))).contiguous(), 1.0)
+    e = (rel(host(gp), rgp), rel(host(gq), rgq), abs(dA - rdA) / abs(rdA))
+    print("checkpointed state-loss gradient vs oracle:", e)
+    assert max(e) <= 1e-12, e
+
+
+def test_checkpointed_gradient_central_differences_and_interval_invariance():
+    grid, n = _adjoint_case()
+    g = T.Grid(**grid)
+    sl = STATE_LOSS
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    y = to_dev(W.target_noise((n, g.nth), 0.05, seed=4))
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+
+    def loss(p, q, A, interval=0):
+        eng.set_amplitude(A)
+        eng.set_state(p, q)
+        w, ls = eng.forward_checkpointed(n, interval=interval, state_loss=sl)
+        return float(torch.sum(torch.abs(w - y) ** 2)) + ls, w
+
+    P0, Q0 = to_dev(phi0), to_dev(pi0)
+    grads = []
+    for interval in (0, 13, n):
+        L0, w = loss(P0, Q0, 1.0, interval)
+        grads.append(eng.backward_checkpointed((2.0 * (w - y)).contiguous(), 1.0))
+    for gr in grads[1:]:
+        assert torch.equal(gr[0], grads[0][0]) and torch.equal(gr[1], grads[0][1]) and gr[2] == grads[0][2]
+    gp, gq, gA = grads[0]
+    h = 1e-3 * np.sqrt(float(torch.sum(torch.abs(P0) ** 2) + torch.sum(torch.abs(Q0) ** 2) + 1.0))
+    for vp, vq, vA in W.fd_directions(g.nth, g.nr, ndir=4, seed=45):
+        Vp, Vq = to_dev(vp), to_dev(vq)
+        fd = (loss(P0 + h * Vp, Q0 + h * Vq, 1.0 + h * vA)[0] - loss(P0 - h * Vp, Q0 - h * Vq, 1.0 - h * vA)[0]) / (2 * h)
+        ad = float(torch.real(torch.vdot(gp.flatten(), Vp.flatten()) + torch.vdot(gq.flatten(), Vq.flatten()))) + gA * vA
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-8 * L0), (fd, ad)
+
+
+def test_autograd_checkpointed_function():
+    from paper_1001_3631_amd.autograd import TeukEvolveCheckpointed
+    grid, n = _adjoint_case(60)
+    g = T.Grid(**grid)
+    sl = dict(STATE_LOSS, n_lo=10, n_hi=50)
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    P0 = to_dev(phi0).requires_grad_(True)
+    Q0 = to_dev(pi0).requires_grad_(True)
+    A = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = to_dev(W.target_noise((n, g.nth), 0.05, seed=4))
+    w, ls = TeukEvolveCheckpointed.apply(P0, Q0, A, eng, n, sl, 0)
+    L = torch.sum(torch.abs(w - y) ** 2) + 3.0 * ls
+    L.backward()
+    eng.set_state(to_dev(phi0), to_dev(pi0))
+    w2, _ = eng.forward_checkpointed(n, 0, sl)
+    gp, gq, gA = eng.backward_checkpointed((2.0 * (w2 - y)).contiguous(), 3.0)
+    assert rel(host(P0.grad), host(gp)) <= 1e-13 and rel(host(Q0.grad), host(gq)) <= 1e-13
+    assert abs(float(A.grad) - gA) <= 1e-13 * abs(gA)
+
+
+# ---------------------------------------------------------------------------
+# Full-size adjoint workload: 3200 x 64, a = 0.7, 20000 iterations
+# ---------------------------------------------------------------------------
+
+def _adjoint_fullsize():
+    cfg = W.ADJOINT
+    grid, n = cfg["grid"], cfg["steps"]
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, cfg["source"], n)
+    return cfg, grid, n, eng
+
+
+def test_adjoint_fullsize_one_reverse_iteration_against_oracle():
+    """A reverse sweep of 200 iterations from a seeded lambda on the GPU, then
+    one more GPU reverse iteration against one oracle reverse iteration
+    applied to the same GPU lambda (whole field and dL/dA)."""
+    cfg, grid, n, eng = _adjoint_fullsize()
+    g = T.Grid(**grid)
+    lp, lq = W.random_state(g.nth, g.nr, seed=51)
+    m0 = 5000
+    eng.adjoint_begin(m0 + 200, to_dev(lp), to_dev(lq))
+    eng.adjoint_step(200)
+    p0, q0, _ = eng.adjoint_get(want_dA=False)
+    p0, q0 = host(p0), host(q0)
+    eng.adjoint_begin(m0, to_dev(p0), to_dev(q0))
+    eng.adjoint_step(1)
+    p1, q1, dA = eng.adjoint_get()
+    src = oracle_source(g, cfg["source"], n)
+    rp, rq, rdA = T.adjoint_step(g, p0, q0, m0 - 1, src)
+    assert rel(host(p1), rp) <= 1e-13 and rel(host(q1), rq) <= 1e-13
+    assert abs(dA - rdA) <= 1e-12 * abs(rdA)
+
+
+def test_adjoint_fullsize_gradient_vs_central_differences_32_directions():
+    """Loss sum |w - y|^2 against a target from the same system with A = 1.25
+    and the pulse at 52M plus 1 % seeded noise; the adjoint gradient with
+    respect to all initial data and A against central differences along 32
+    seeded unit directions, h = 1e-3 |x| (the loss is quadratic, so the
+    differences are exact up to rounding)."""
+    cfg, grid, n, eng = _adjoint_fullsize()
+    nth, nr = grid["nth"], grid["nr"]
+    tg = cfg["target"]
+    eng.init_pulse(tg["center"], cfg["pulse"]["width"], cfg["pulse"]["amplitude"])
+    eng.set_amplitude(tg["amplitude"])
+    y = eng.step(n)
+    rms = float(torch.sqrt(torch.mean(torch.abs(y) ** 2)))
+    y = y + to_dev(W.target_noise((n, nth), tg["noise_rel"] * rms, seed=tg["seed"]))
+    eng.init_pulse(**cfg["pulse"])
+    P0, Q0 = [t.clone() for t in eng.get_state()]
+
+    def loss(p, q, A):
+        eng.set_amplitude(A)
+        eng.set_state(p, q)
+        w = eng.step(n)
+        return float(torch.sum(torch.abs(w - y) ** 2)), w
+
+    L0, w = loss(P0, Q0, 1.0)
+    gw = (2.0 * (w - y)).contiguous()
+    eng.adjoint_begin(n, gw=gw)
+    eng.adjoint_step(n)
+    gp, gq, gA = eng.adjoint_get()
+    h = 1e-3 * float(torch.sqrt(torch.sum(torch.abs(P0) ** 2) + torch.sum(torch.abs(Q0) ** 2) + 1.0))
+    worst = 0.0
+    for vp, vq, vA in W.fd_directions(nth, nr, ndir=cfg["fd"]["ndir"], seed=cfg["fd"]["seed"]):
+        Vp, Vq = to_dev(vp), to_dev(vq)
+        fd = (loss(P0 + h * Vp, Q0 + h * Vq, 1.0 + h * vA)[0] - loss(P0 - h * Vp, Q0 - h * Vq, 1.0 - h * vA)[0]) / (2 * h)
+        ad = float(torch.real(torch.vdot(gp.flatten(), Vp.flatten()) + torch.vdot(gq.flatten(), Vq.flatten()))) + gA * vA
+        worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
+    print("adjoint_3200x64: worst relative |FD - adjoint| over 32 directions:", worst)
+    assert worst <= 1e-6
