@@ -16,12 +16,23 @@ namespace teuk {
 
 namespace {
 
-__device__ __forceinline__ double2 shfl_dn1(double2 v) {
-    return make_double2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
+// Cross-lane moves with DPP wave shifts (no LDS traffic): from_next gives lane
+// l the value of lane l+1 (lane 63 keeps its own), from_prev the value of lane
+// l-1 (lane 0 keeps its own).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double2 shfl_up1(double2 v) {
-    return make_double2(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
+__device__ __forceinline__ double2 from_next(double2 v) {
+    return make_double2(dpp_move<0x130>(v.x), dpp_move<0x130>(v.y));   // wave_shl:1
 }
+__device__ __forceinline__ double2 from_prev(double2 v) {
+    return make_double2(dpp_move<0x138>(v.x), dpp_move<0x138>(v.y));   // wave_shr:1
+}
+
+
 
 __device__ __forceinline__ double2 src_lookup(const double2* __restrict__ tab, int c0, int r0,
                                               int win_r, int win_t, int col, int row) {
@@ -94,7 +105,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
             }
             uP[t] = p;
             uQ[t] = q;
-            const double2 pN = shfl_dn1(p), qN = shfl_dn1(q);
+            const double2 pN = from_next(p), qN = from_next(q);
             sP[t] = c_add(p, pN);
             sQ[t] = c_add(q, qN);
             dP[t] = c_sub(pN, p);
@@ -119,11 +130,11 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                 if (jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
                     hP[t - 3] = pole_value(P.even, hP[t - 2], hP[t - 1]);
                     hQ[t - 3] = pole_value(P.even, hQ[t - 2], hQ[t - 1]);
-                    gP[t - 3] = shfl_up1(hP[t - 3]);
-                    gQ[t - 3] = shfl_up1(hQ[t - 3]);
+                    gP[t - 3] = from_prev(hP[t - 3]);
+                    gQ[t - 3] = from_prev(hQ[t - 3]);
                 }
-                gP[t - 1] = shfl_up1(hP[t - 1]);
-                gQ[t - 1] = shfl_up1(hQ[t - 1]);
+                gP[t - 1] = from_prev(hP[t - 1]);
+                gQ[t - 1] = from_prev(hQ[t - 1]);
             }
 
             // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
