@@ -13,6 +13,10 @@ Also reported on the same JSON line:
                 stencil launch of one extra evolution;
   hbm_grid      the same physics on 12800 x 256 (larger than the last-level
                 cache), GPts/s and algorithmic GB/s;
+  batched       64 independent instances of uneven size (seeded m, a, grid
+                level, pulse centre), 10000 iterations each, in one persistent
+                launch per evolution captured in a HIP graph, against the
+                plain stepper running the same instances one after another;
   cpu_baseline  the FP64 oracle on the host for a bounded number of
                 iterations of the same workload.
 """
@@ -56,6 +60,8 @@ def parse():
     ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance workload")
+    ap.add_argument("--batched-iterations", type=int, default=10000)
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -139,6 +145,55 @@ def adjoint_ratio(args):
     return {"workload": cfg["name"], "iterations": n, "forward_s": round(tf, 4), "adjoint_s": round(ta, 4),
             "ratio": round(ta / tf, 3), "forward_plus_backward_with_recompute_s": round(tc, 4),
             "ratio_with_recompute": round((tc - tf) / tf, 3)}
+
+
+def batched(args):
+    """The batched workload: persistent batched launch vs the plain stepper."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    from paper_1001_3631_amd.engine import Batch, Engine
+    inst = W.batched_instances()
+    n = args.batched_iterations
+    grids = [it["grid"] for it in inst]
+    pts = sum(g["nr"] * g["nth"] for g in grids)
+    b = Batch(grids)
+    tune = b.autotune(None)
+    waves = [torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda") for g in grids]
+
+    def evolve():
+        for e, it in zip(b.instances, inst):
+            e.init_pulse(**it["pulse"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(n, out=waves)
+        b.sync()
+        return time.perf_counter() - t0
+
+    evolve()                                        # captures the graph for n iterations
+    tb = evolve()
+    for e in b.instances:
+        e.check_finite()
+    b.close()
+    del waves
+
+    # plain stepper, one instance after another, same iterations and extraction
+    tp = 0.0
+    for it in inst:
+        eng = Engine(**it["grid"])
+        eng.autotune(None)
+        w = torch.empty((n, it["grid"]["nth"]), dtype=torch.complex128, device="cuda")
+        eng.init_pulse(**it["pulse"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        eng.step(n, out=w)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t1
+        eng.close()
+    return {"workload": "batched_64_instances_seed3", "instances": len(grids), "points": pts,
+            "iterations": n, "seg_rows": tune[0][0],
+            "batched_s": round(tb, 3), "batched_gpts": round(pts * n / tb / 1e9, 3),
+            "plain_sequential_s": round(tp, 3), "plain_gpts": round(pts * n / tp / 1e9, 3),
+            "batched_over_plain": round(tp / tb, 3)}
 
 
 def cpu_baseline(cfg, iters):
@@ -241,6 +296,10 @@ def main():
     if not args.no_adjoint:
         extra["adjoint"] = adjoint_ratio(args)
         print(f"[bench] adjoint: {extra['adjoint']}", file=sys.stderr, flush=True)
+
+    if not args.no_batched:
+        extra["batched"] = batched(args)
+        print(f"[bench] batched: {extra['batched']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

@@ -211,14 +211,98 @@ int teuk_check_finite(teuk_ctx* ctx);
 
 /* Launch configuration of the stencil (results are bitwise identical for
  * every valid setting; only speed changes).
- *   seg_rows  theta rows per wave segment of the streaming stencil: 4, 8 or 16.
- *             The default is chosen from the grid size at teuk_init_grid. */
+ *   seg_rows  theta rows per wave segment of the streaming stencil.
+ *   k_steps   iterations per launch (temporal blocking).  1: the single-step
+ *             kernel, seg_rows 4, 8 or 16.  k > 1: the blocked kernel runs k
+ *             consecutive iterations (half and full steps, boundary rows,
+ *             source and extraction of each) in one launch, reading u^n from
+ *             and writing u^{n+k} to HBM once; (seg_rows, k_steps) one of
+ *             (4, 2), (8, 2), (4, 4).  teuk_step_n runs floor(nsteps / k)
+ *             blocks and the remainder as single iterations.
+ * The default (k_steps 1, seg_rows from the grid size) is set by
+ * teuk_init_grid; teuk_autotune chooses by measurement.  EINVAL for any
+ * other pair. */
 typedef struct {
     int32_t seg_rows;
+    int32_t k_steps;
 } teuk_tuning;
 
 int teuk_set_tuning(teuk_ctx* ctx, const teuk_tuning* t);
 int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
+
+/* Autotuner over the launch configurations above.
+ * Times every valid (seg_rows, k_steps) pair on this context's grid with HIP
+ * events (warm-up, then the best of three timed runs of a fixed number of
+ * iterations, without source or extraction), keeps the fastest as the
+ * context's tuning, and leaves the state, iteration count and source batch
+ * as they were (the state is saved to and restored from temporary device
+ * planes, allocated and freed inside the call; synchronizes the stream).
+ *   cache_path  host string or NULL.  A text file of lines
+ *               "<key>\t<seg_rows>\t<k_steps>\t<us per iteration>", where the
+ *               key names the device architecture, nr, nth, whether a != 0
+ *               and whether the dissipation is on, and a hash of the kernel
+ *               sources the library was built from.  If a line with this
+ *               context's key exists its pair is applied without measuring;
+ *               otherwise the measured choice is appended (the file is
+ *               created if missing).  Unreadable/unwritable file: EINVAL.
+ *   table       host array of capacity entries or NULL: receives every
+ *               measured pair (or the one cached pair), fastest first;
+ *               *count (host, may be NULL) = entries written.
+ * ENOMEM if the temporary planes cannot be allocated. */
+typedef struct {
+    int32_t seg_rows;
+    int32_t k_steps;
+    double us_per_iteration;
+} teuk_tune_entry;
+
+int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
+                  int32_t* count);
+
+/* Batched stepping: many independent instances (each its own M, a, s, m,
+ * grid and state) advanced together by ONE persistent kernel launch,
+ * captured in a HIP graph together with a small kernel that resets its work
+ * counters.  Work items are tiles (instance, strip of 62 r* columns, theta
+ * segment of seg_rows rows) of one iteration; persistent waves take them from
+ * a global counter in iteration-major order, and each item waits on per-tile
+ * completion counters of its neighbouring tiles (the iteration's data
+ * dependences, Sec. 3.2 half and full steps) instead of a launch boundary.
+ * Every point is evaluated by the same device code as teuk_step_n, so an
+ * instance's results are bitwise equal to stepping it alone.
+ *
+ * teuk_batch_create: n >= 1 descriptors (host array); every instance gets a
+ *   context as from teuk_init_grid on hip_stream (validation as there; the
+ *   message names the failing instance).  Synchronizes.
+ * teuk_batch_instance: borrowed context of instance k (0 <= k < n), for
+ *   teuk_set_state / teuk_init_pulse / teuk_get_state / teuk_step_n / ...;
+ *   teuk_destroy refuses it (EINVAL), teuk_batch_destroy frees it.
+ * teuk_batch_set_tuning / get_tuning: theta rows per segment, 4, 8 or 16
+ *   (EINVAL otherwise); synchronizes.  The default is chosen from the
+ *   batch's total tile count at creation.
+ * teuk_batch_step_n: nsteps (0 <= nsteps <= INT32_MAX) iterations of every
+ *   instance.  waveforms = NULL or a host array of n device pointers, each
+ *   NULL or nsteps * nth complex128 (the extraction column after every
+ *   iteration, as teuk_step_n).  Instances must carry no source (EINVAL).
+ *   Asynchronous; the graph for (nsteps, seg_rows) is captured on first use
+ *   and cached.
+ * teuk_batch_sync: synchronizes the stream and reports a launch that gave up
+ *   (TEUK_EDEVICE): a dependency wait that exceeds 2 s of device wall clock
+ *   makes every wave of that launch, and of launches queued after it, exit
+ *   early, leaving the states invalid.  Reading the report clears it.
+ * teuk_batch_autotune: as teuk_autotune over seg_rows (k_steps is 1 for
+ *   batches), timing 8 batched iterations per variant, all instance states
+ *   saved and restored; cache key = architecture, the instance shapes and
+ *   the kernel sources. */
+typedef struct teuk_batch teuk_batch;
+
+int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, teuk_batch** out);
+int teuk_batch_destroy(teuk_batch* batch);
+int teuk_batch_instance(teuk_batch* batch, int32_t k, teuk_ctx** out);
+int teuk_batch_set_tuning(teuk_batch* batch, int32_t seg_rows);
+int teuk_batch_get_tuning(const teuk_batch* batch, int32_t* seg_rows);
+int teuk_batch_step_n(teuk_batch* batch, int64_t nsteps, void* const* waveforms);
+int teuk_batch_sync(teuk_batch* batch);
+int teuk_batch_autotune(teuk_batch* batch, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
+                        int32_t* count);
 
 /* Measurement aid: while enabled, every stencil launch made by teuk_step_n
  * records a pair of HIP events at the start and end of that kernel's

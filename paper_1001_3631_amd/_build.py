@@ -1,5 +1,6 @@
 """Build the HIP library libteuk.so in-tree for gfx950 (hipcc)."""
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -9,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libteuk.so")
 
-SOURCES = ["geometry.cpp", "stencil.hip", "adjoint.hip", "capi.cpp"]
+SOURCES = ["geometry.cpp", "stencil.hip", "adjoint.hip", "capi.cpp", "batch.cpp"]
 
 # -ffp-contract=off: every fused multiply-add is written explicitly, so every
 # kernel variant rounds identically.  Packed FP32 instructions are disabled.
@@ -27,10 +28,22 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+def source_hash():
+    """Hash of the kernel and library sources; keys the autotuner's cache."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False, extra_flags=()):
     """Compile every source into libteuk.so (always recompiles)."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + list(extra_flags) + ["-I", os.path.join(ROOT, "include"), "-o", tmp]
+    cmd = [hipcc()] + FLAGS + list(extra_flags) + [f'-DTEUK_SOURCE_HASH="{source_hash()}"']
+    cmd += ["-I", os.path.join(ROOT, "include"), "-o", tmp]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -45,7 +45,12 @@ class Info(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("seg_rows", ctypes.c_int32)]
+    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32),
+                ("us_per_iteration", ctypes.c_double)]
 
 
 class SourceDesc(ctypes.Structure):
@@ -90,6 +95,17 @@ SIGNATURES = {
     "teuk_check_finite": (ctypes.c_int, [_CTX]),
     "teuk_set_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
     "teuk_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
+    "teuk_autotune": (ctypes.c_int, [_CTX, ctypes.c_char_p, ctypes.POINTER(TuneEntry), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]),
+    "teuk_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GridDesc), _P, ctypes.POINTER(_CTX)]),
+    "teuk_batch_destroy": (ctypes.c_int, [_CTX]),
+    "teuk_batch_instance": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(_CTX)]),
+    "teuk_batch_set_tuning": (ctypes.c_int, [_CTX, ctypes.c_int32]),
+    "teuk_batch_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
+    "teuk_batch_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, ctypes.POINTER(_P)]),
+    "teuk_batch_sync": (ctypes.c_int, [_CTX]),
+    "teuk_batch_autotune": (ctypes.c_int, [_CTX, ctypes.c_char_p, ctypes.POINTER(TuneEntry), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
     "teuk_set_kernel_timing": (ctypes.c_int, [_CTX, ctypes.c_int]),
     "teuk_kernel_timing": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),

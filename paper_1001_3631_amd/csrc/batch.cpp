@@ -1,0 +1,480 @@
+// C ABI of batched stepping: many independent instances advanced by one
+// persistent launch captured in a HIP graph (declared in include/teuk.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/teuk.h"
+#include "ctx.h"
+#include "kernels.h"
+
+#ifndef TEUK_SOURCE_HASH
+#define TEUK_SOURCE_HASH "unversioned"
+#endif
+
+using teuk_detail::fail;
+using teuk_detail::hip_fail;
+
+namespace {
+
+constexpr int kGraphCache = 8;          // captured (rounds, seg_rows) graphs kept per batch
+constexpr double kWaitLimitSeconds = 2.0;
+
+struct BatchGraph {
+    int64_t rounds = 0;
+    int seg = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct teuk_batch {
+    std::vector<teuk_ctx*> inst;
+    hipStream_t stream = nullptr;       // caller's stream: every launch and copy
+    hipStream_t cap = nullptr;          // private stream used only to capture graphs
+    int seg_rows = 8;
+    int ntiles = 0;                     // tiles per iteration at seg_rows
+    int max_tiles = 0;                  // at the smallest segment (allocation size)
+    int waves = 0;                      // persistent waves per launch
+    int resident_waves = 0;             // 8 per CU (two per SIMD at the kernel's register use)
+    long long wait_limit = 0;
+    teuk::BatchInstance* h_inst[2] = {nullptr, nullptr};   // pinned, alternate calls
+    hipEvent_t h_inst_free[2] = {nullptr, nullptr};        // copy out of h_inst[k] finished
+    int slot = 0;
+    teuk::BatchInstance* d_inst = nullptr;
+    int4* d_tiles = nullptr;
+    int* d_done = nullptr;
+    unsigned long long* d_ticket = nullptr;
+    int* d_abort = nullptr;
+    std::vector<BatchGraph> graphs;
+};
+
+namespace {
+
+int tiles_for(const teuk_batch* b, int seg) {
+    long total = 0;
+    for (const teuk_ctx* c : b->inst) total += static_cast<long>(c->nstrips) * ((c->G.nth - 3) / seg + 1);
+    return total > INT_MAX ? -1 : static_cast<int>(total);
+}
+
+void drop_graphs(teuk_batch* b) {
+    for (auto& g : b->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    b->graphs.clear();
+}
+
+void free_batch(teuk_batch* b) {
+    (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (teuk_ctx* c : b->inst) teuk_detail::destroy_ctx(c);
+    b->inst.clear();
+    for (int k = 0; k < 2; ++k) {
+        if (b->h_inst[k]) (void)hipHostFree(b->h_inst[k]);
+        if (b->h_inst_free[k]) (void)hipEventDestroy(b->h_inst_free[k]);
+    }
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_done);
+    (void)hipFree(b->d_ticket);
+    (void)hipFree(b->d_abort);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+// Tile list for a segment length: instance-major, then strip, then segment;
+// tile index = position in the list (also the index of its done counter).
+int set_batch_tiles(teuk_batch* b, int seg) {
+    std::vector<int4> tiles;
+    tiles.reserve(b->max_tiles);
+    for (size_t k = 0; k < b->inst.size(); ++k) {
+        teuk_ctx* c = b->inst[k];
+        const int nseg = (c->G.nth - 3) / seg + 1;
+        for (int s = 0; s < c->nstrips; ++s)
+            for (int q = 0; q < nseg; ++q)
+                tiles.push_back(make_int4(static_cast<int>(k), s, q, static_cast<int>(tiles.size())));
+    }
+    HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice),
+            "batch tiles");
+    b->seg_rows = seg;
+    b->ntiles = static_cast<int>(tiles.size());
+    b->waves = std::max(1, std::min(b->resident_waves, b->ntiles));
+    return TEUK_OK;
+}
+
+// Instance table of the next launch: static fields plus each instance's
+// current level and waveform pointer.  Alternates between two pinned
+// buffers; a buffer is rewritten only after its previous copy has finished.
+int upload_instances(teuk_batch* b, void* const* waveforms) {
+    const int k = b->slot;
+    b->slot ^= 1;
+    HIP_TRY(hipEventSynchronize(b->h_inst_free[k]), "batch table reuse");
+    teuk::BatchInstance* h = b->h_inst[k];
+    int tile0 = 0;
+    for (size_t j = 0; j < b->inst.size(); ++j) {
+        const teuk_ctx* c = b->inst[j];
+        const teuk::Geometry& G = c->G;
+        teuk::BatchInstance& I = h[j];
+        for (int l = 0; l < 2; ++l)
+            for (int f = 0; f < 2; ++f) I.plane[l][f] = c->plane[l][f];
+        I.rnode = c->d_rnode;
+        I.rhalf = c->d_rhalf;
+        I.rows = c->d_rows;
+        I.nr = G.nr;
+        I.nth = G.nth;
+        I.ld = c->ld;
+        I.rpitch = G.nr;
+        I.nstrips = c->nstrips;
+        I.nseg = (G.nth - 3) / b->seg_rows + 1;
+        I.dt = G.dt;
+        I.inv_hr = 1.0 / G.h_r;
+        I.ko_c = c->ko_c;
+        I.even = (std::abs(G.m) % 2 == 0);
+        I.i_ext = G.i_ext;
+        I.cur = c->cur;
+        I.tile0 = tile0;
+        I.wave = waveforms ? static_cast<double2*>(waveforms[j]) : nullptr;
+        tile0 += I.nstrips * I.nseg;
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_inst, h, sizeof(teuk::BatchInstance) * b->inst.size(), hipMemcpyHostToDevice,
+                           b->stream),
+            "batch table upload");
+    HIP_TRY(hipEventRecord(b->h_inst_free[k], b->stream), "batch table event");
+    return TEUK_OK;
+}
+
+// Captured graph for (rounds, seg_rows): reset the counters, then the
+// persistent launch.  Kept in a small cache.
+int graph_for(teuk_batch* b, int64_t rounds, hipGraphExec_t* out) {
+    for (auto& g : b->graphs)
+        if (g.rounds == rounds && g.seg == b->seg_rows) {
+            *out = g.exec;
+            return TEUK_OK;
+        }
+    if (static_cast<int>(b->graphs.size()) == kGraphCache) {
+        (void)hipGraphExecDestroy(b->graphs.front().exec);
+        (void)hipGraphDestroy(b->graphs.front().graph);
+        b->graphs.erase(b->graphs.begin());
+    }
+    teuk::BatchParams B;
+    B.inst = b->d_inst;
+    B.tiles = b->d_tiles;
+    B.ntiles = b->ntiles;
+    B.rounds = static_cast<int>(rounds);
+    B.ticket = b->d_ticket;
+    B.done = b->d_done;
+    B.abort = b->d_abort;
+    B.wait_limit = b->wait_limit;
+    BatchGraph g;
+    g.rounds = rounds;
+    g.seg = b->seg_rows;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "batch capture begin");
+    hipError_t e1 = teuk::launch_batch_reset(B, b->cap);
+    hipError_t e2 = (e1 == hipSuccess) ? teuk::launch_batch(B, b->seg_rows, b->waves, b->cap) : e1;
+    hipError_t e3 = hipStreamEndCapture(b->cap, &g.graph);
+    if (e2 != hipSuccess) {
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        return hip_fail(e2, "batch capture");
+    }
+    if (e3 != hipSuccess) return hip_fail(e3, "batch capture end");
+    hipError_t e4 = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e4 != hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        return hip_fail(e4, "batch graph instantiate");
+    }
+    b->graphs.push_back(g);
+    *out = g.exec;
+    return TEUK_OK;
+}
+
+int check_batch(const teuk_batch* b) {
+    if (b == nullptr) return fail(TEUK_EINVAL, "null batch");
+    return TEUK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, teuk_batch** out) {
+    if (out == nullptr || descs == nullptr) return fail(TEUK_EINVAL, "null descriptors or output");
+    *out = nullptr;
+    if (n < 1) return fail(TEUK_EINVAL, "a batch needs at least one instance");
+    teuk_batch* b = new (std::nothrow) teuk_batch();
+    if (b == nullptr) return fail(TEUK_ENOMEM, "host allocation failed");
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    for (int32_t k = 0; k < n; ++k) {
+        teuk_ctx* c = nullptr;
+        if (int rc = teuk_init_grid(&descs[k], hip_stream, &c)) {
+            const std::string msg = "instance " + std::to_string(k) + ": " + teuk_detail::g_last_error;
+            free_batch(b);
+            return fail(rc, msg);
+        }
+        c->in_batch = true;
+        b->inst.push_back(c);
+    }
+    b->max_tiles = tiles_for(b, 4);
+    if (b->max_tiles < 0) {
+        free_batch(b);
+        return fail(TEUK_EINVAL, "too many tiles in one batch");
+    }
+    int dev = 0, cus = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->h_inst[k]), sizeof(teuk::BatchInstance) * n);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->h_inst_free[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b->h_inst_free[k], b->stream);
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->d_inst, sizeof(teuk::BatchInstance) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(int4) * b->max_tiles);
+    if (e == hipSuccess) e = hipMalloc(&b->d_done, sizeof(int) * b->max_tiles);
+    if (e == hipSuccess) e = hipMalloc(&b->d_ticket, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(b->d_abort, 0, sizeof(int));
+    if (e != hipSuccess) {
+        free_batch(b);
+        return fail(TEUK_ENOMEM, std::string("batch setup: ") + hipGetErrorString(e));
+    }
+    b->resident_waves = 8 * std::max(cus, 1);
+    b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * std::max(khz, 1));
+    // default segment: the single-instance rule applied to the whole batch
+    const int seg = (static_cast<long>(tiles_for(b, 8)) >= 1024) ? 8 : 4;
+    if (int rc = set_batch_tiles(b, seg)) {
+        const std::string msg = teuk_detail::g_last_error;
+        free_batch(b);
+        return fail(rc, msg);
+    }
+    *out = b;
+    return TEUK_OK;
+}
+
+int teuk_batch_destroy(teuk_batch* b) {
+    if (b == nullptr) return TEUK_OK;
+    free_batch(b);
+    return TEUK_OK;
+}
+
+int teuk_batch_instance(teuk_batch* b, int32_t k, teuk_ctx** out) {
+    if (int rc = check_batch(b)) return rc;
+    if (out == nullptr) return fail(TEUK_EINVAL, "null output");
+    if (k < 0 || k >= static_cast<int32_t>(b->inst.size())) return fail(TEUK_EINVAL, "instance index out of range");
+    *out = b->inst[k];
+    return TEUK_OK;
+}
+
+int teuk_batch_set_tuning(teuk_batch* b, int32_t seg_rows) {
+    if (int rc = check_batch(b)) return rc;
+    if (!teuk::valid_segment_rows(seg_rows)) return fail(TEUK_EINVAL, "seg_rows must be 4, 8 or 16");
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch tuning");
+    return set_batch_tiles(b, seg_rows);
+}
+
+int teuk_batch_get_tuning(const teuk_batch* b, int32_t* seg_rows) {
+    if (int rc = check_batch(b)) return rc;
+    if (seg_rows == nullptr) return fail(TEUK_EINVAL, "null output");
+    *seg_rows = b->seg_rows;
+    return TEUK_OK;
+}
+
+int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
+    if (int rc = check_batch(b)) return rc;
+    if (nsteps < 0 || nsteps > INT_MAX) return fail(TEUK_EINVAL, "nsteps out of range");
+    if (nsteps == 0) return TEUK_OK;
+    for (size_t k = 0; k < b->inst.size(); ++k)
+        if (b->inst[k]->has_src)
+            return fail(TEUK_EINVAL, "batched stepping evolves homogeneous instances; instance " +
+                                         std::to_string(k) + " has a source");
+    if (static_cast<unsigned long long>(nsteps) * static_cast<unsigned long long>(b->ntiles) >= (1ull << 62))
+        return fail(TEUK_EINVAL, "too many work items in one launch");
+    hipGraphExec_t exec = nullptr;
+    if (int rc = graph_for(b, nsteps, &exec)) return rc;
+    if (int rc = upload_instances(b, waveforms)) return rc;
+    HIP_TRY(hipGraphLaunch(exec, b->stream), "batch graph launch");
+    for (teuk_ctx* c : b->inst) {
+        c->cur ^= static_cast<int>(nsteps & 1);
+        c->steps_done += nsteps;
+    }
+    return TEUK_OK;
+}
+
+int teuk_batch_sync(teuk_batch* b) {
+    if (int rc = check_batch(b)) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, b->d_abort, sizeof(int), hipMemcpyDeviceToHost), "batch abort flag");
+    if (flag != 0) {
+        HIP_TRY(hipMemset(b->d_abort, 0, sizeof(int)), "batch abort flag clear");
+        return fail(TEUK_EDEVICE, "batched launch aborted: a dependency wait exceeded its limit; "
+                                  "instance states are invalid");
+    }
+    return TEUK_OK;
+}
+
+int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
+                        int32_t* count) {
+    if (int rc = check_batch(b)) return rc;
+    if (count != nullptr) *count = 0;
+    if (table != nullptr && capacity < 0) return fail(TEUK_EINVAL, "negative table capacity");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "autotune device");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "autotune device properties");
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    // key: architecture, the instance shapes, and the kernel sources
+    unsigned long long h = 1469598103934665603ull;   // FNV-1a over the shapes
+    auto mix = [&](long long v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= static_cast<unsigned long long>((v >> (8 * k)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const teuk_ctx* c : b->inst) {
+        mix(c->G.nr);
+        mix(c->G.nth);
+        mix(c->G.a != 0.0);
+        mix(c->ko_c != 0.0);
+    }
+    char keybuf[256];
+    std::snprintf(keybuf, sizeof(keybuf), "%s batch n=%zu shapes=%016llx src=%s", arch.c_str(), b->inst.size(), h,
+                  TEUK_SOURCE_HASH);
+    const std::string key = keybuf;
+    auto emit = [&](const std::vector<teuk_tune_entry>& v) {
+        int32_t w = 0;
+        if (table != nullptr)
+            for (const auto& e : v)
+                if (w < capacity) table[w++] = e;
+        if (count != nullptr) *count = w;
+    };
+    if (cache_path != nullptr) {
+        std::ifstream f(cache_path);
+        std::string line;
+        bool found = false;
+        teuk_tune_entry hit{};
+        while (f && std::getline(f, line)) {
+            std::istringstream ls(line);
+            std::string k, seg, kk, us;
+            if (!std::getline(ls, k, '\t') || !std::getline(ls, seg, '\t') || !std::getline(ls, kk, '\t') ||
+                !std::getline(ls, us, '\t'))
+                continue;
+            if (k != key) continue;
+            const int s = std::atoi(seg.c_str());
+            if (teuk::valid_segment_rows(s) && std::atoi(kk.c_str()) == 1) {
+                hit = {s, 1, std::atof(us.c_str())};
+                found = true;
+            }
+        }
+        if (found) {
+            if (hit.seg_rows != b->seg_rows)
+                if (int rc = teuk_batch_set_tuning(b, hit.seg_rows)) return rc;
+            emit({hit});
+            return TEUK_OK;
+        }
+    }
+
+    // save every instance's current level, time each variant, restore
+    const int seg0 = b->seg_rows;
+    std::vector<double2*> save;
+    auto release = [&]() {
+        for (double2* p : save) (void)hipFree(p);
+        save.clear();
+    };
+    for (teuk_ctx* c : b->inst) {
+        const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+        for (int f = 0; f < 2; ++f) {
+            double2* p = nullptr;
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                release();
+                return fail(TEUK_ENOMEM, std::string("batch autotune planes: ") + hipGetErrorString(e));
+            }
+            save.push_back(p);
+            HIP_TRY(hipMemcpyAsync(p, c->plane[c->cur][f], bytes, hipMemcpyDeviceToDevice, b->stream),
+                    "batch autotune save");
+        }
+    }
+    std::vector<int> cur0;
+    std::vector<int64_t> steps_done0;
+    for (teuk_ctx* c : b->inst) {
+        cur0.push_back(c->cur);
+        steps_done0.push_back(c->steps_done);
+    }
+    auto restore = [&]() {
+        (void)hipStreamSynchronize(b->stream);
+        for (size_t k = 0; k < b->inst.size(); ++k) {
+            teuk_ctx* c = b->inst[k];
+            const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+            c->cur = cur0[k];
+            c->steps_done = steps_done0[k];
+            for (int f = 0; f < 2; ++f)
+                (void)hipMemcpyAsync(c->plane[c->cur][f], save[2 * k + f], bytes, hipMemcpyDeviceToDevice,
+                                     b->stream);
+        }
+        (void)hipStreamSynchronize(b->stream);
+        release();
+    };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        restore();
+        return hip_fail(e, "batch autotune events");
+    }
+    std::vector<teuk_tune_entry> cand;
+    for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, 0.0});
+    constexpr int kRounds = 8, kReps = 3;
+    int rc = TEUK_OK;
+    for (auto& t : cand) {
+        rc = teuk_batch_set_tuning(b, t.seg_rows);
+        if (rc == TEUK_OK) rc = teuk_batch_step_n(b, kRounds, nullptr);   // warm-up (and capture)
+        double best = 1e300;
+        for (int r = 0; rc == TEUK_OK && r < kReps; ++r) {
+            float ms = 0.0f;
+            e = hipEventRecord(ev[0], b->stream);
+            if (e == hipSuccess) rc = teuk_batch_step_n(b, kRounds, nullptr);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventRecord(ev[1], b->stream);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess && rc == TEUK_OK) rc = hip_fail(e, "batch autotune timing");
+            best = std::min(best, 1e3 * static_cast<double>(ms) / kRounds);
+        }
+        if (rc == TEUK_OK) rc = teuk_batch_sync(b);
+        if (rc != TEUK_OK) break;
+        t.us_per_iteration = best;
+    }
+    const std::string msg = teuk_detail::g_last_error;
+    restore();
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (rc != TEUK_OK) {
+        (void)teuk_batch_set_tuning(b, seg0);
+        return fail(rc, msg);
+    }
+    std::stable_sort(cand.begin(), cand.end(), [](const teuk_tune_entry& x, const teuk_tune_entry& y) {
+        return x.us_per_iteration < y.us_per_iteration;
+    });
+    if (int r2 = teuk_batch_set_tuning(b, cand[0].seg_rows)) return r2;
+    emit(cand);
+    if (cache_path != nullptr) {
+        std::ofstream f(cache_path, std::ios::app);
+        char line[512];
+        std::snprintf(line, sizeof(line), "%s\t%d\t%d\t%.4f\n", key.c_str(), cand[0].seg_rows, 1,
+                      cand[0].us_per_iteration);
+        if (!(f << line)) return fail(TEUK_EINVAL, std::string("cannot append to tuning cache ") + cache_path);
+    }
+    return TEUK_OK;
+}
+
+}  // extern "C"

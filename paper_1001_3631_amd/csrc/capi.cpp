@@ -3,19 +3,23 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/teuk.h"
+#include "ctx.h"
 #include "geometry.h"
 #include "kernels.h"
 
 using teuk::Geometry;
 using teuk::ThetaRow;
 
-namespace {
+namespace teuk_detail {
 
 thread_local std::string g_last_error;
 
@@ -28,65 +32,22 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(TEUK_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                          \
-    do {                                             \
-        hipError_t _e = (expr);                      \
-        if (_e != hipSuccess) return hip_fail(_e, what); \
-    } while (0)
+}  // namespace teuk_detail
+
+using teuk_detail::fail;
+using teuk_detail::g_last_error;
+using teuk_detail::hip_fail;
+
+namespace {
+
+#ifndef TEUK_SOURCE_HASH
+#define TEUK_SOURCE_HASH "unversioned"
+#endif
 
 constexpr int kSourceBatch = 256;   // iterations of source windows per compact pass
 constexpr int kPartSteps = 64;      // adjoint iterations whose dL/dA partials are reduced together
 
 }  // namespace
-
-struct teuk_ctx {
-    Geometry G;
-    hipStream_t stream = nullptr;
-    int ld = 0;
-    double2* plane[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [level][Phi, Pi]
-    int cur = 0;
-    double* d_rnode = nullptr;
-    double* d_rhalf = nullptr;
-    ThetaRow* d_rows = nullptr;
-    int* d_flag = nullptr;
-    double ko_c = 0.0;
-    int nstrips = 0, nseg = 0, seg_rows = 16;
-    int64_t steps_done = 0;
-    // source
-    bool has_src = false;
-    double amplitude = 0.0, sig_r = 0.0, sig_th = 0.0, cut = 0.0;
-    int64_t nsamples = 0;
-    double* d_orbit = nullptr;
-    int win_r = 0, win_t = 0;
-    double2* d_fh = nullptr;
-    double2* d_fn = nullptr;
-    int4* d_org = nullptr;
-    int64_t batch_n0 = -1;
-    int batch_len = 0;
-    double batch_amp = 0.0;
-    // adjoint
-    double2* adj[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    int adj_cur = 0;
-    int64_t adj_clock = -1;
-    double* d_dA = nullptr;        // accumulated dL/dA (device)
-    double* d_dA_part = nullptr;   // per-wave partials of up to kPartSteps iterations
-    int part_items = 0;            // partials per iteration (waves of the adjoint launch)
-    int part_filled = 0;           // iterations written since the last reduction
-    // checkpointed gradient
-    std::vector<double2*> snaps;   // 2 planes per snapshot: [2k] Phi, [2k+1] Pi
-    double2* seg_buf = nullptr;    // Phi on the loss rectangle, one slot per segment iteration
-    size_t seg_buf_bytes = 0;
-    double* d_ls = nullptr;        // accumulated sum |Phi|^2 over the rectangle
-    double* d_ls_part = nullptr;   // per-row partials (nth)
-    bool ckpt_valid = false;
-    teuk_grad_plan ckpt_plan{};
-    // kernel timing (measurement aid)
-    bool timing = false;
-    std::vector<hipEvent_t> ev_start, ev_stop;
-    size_t ev_used = 0;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
-};
 
 namespace {
 
@@ -167,6 +128,16 @@ void free_all(teuk_ctx* c) {
     (void)hipFree(c->d_flag);
 }
 
+}  // namespace
+
+void teuk_detail::destroy_ctx(teuk_ctx* c) {
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+namespace {
+
 int check_ctx(const teuk_ctx* c) {
     if (c == nullptr) return fail(TEUK_EINVAL, "null context");
     return TEUK_OK;
@@ -209,6 +180,14 @@ int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t spa
     return TEUK_OK;
 }
 
+void set_tuning_fields(teuk_ctx* c, int seg, int k) {
+    c->seg_rows = seg;
+    c->k_steps = k;
+    c->nseg = (c->G.nth - 3) / seg + 1;
+    const int w = teuk::block_strip_width(k);
+    c->bstrips = (c->G.nr + w - 1) / w;
+}
+
 int flush_partials(teuk_ctx* c) {
     if (c->part_filled == 0) return TEUK_OK;
     HIP_TRY(teuk::launch_reduce_partials(c->d_dA_part, c->part_items * c->part_filled, c->d_dA, c->stream),
@@ -242,8 +221,7 @@ int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
     c->nstrips = (G.nr + 61) / 62;
     // default segment: 8 rows when that still gives at least one wave per SIMD
     // (256 CUs x 4 SIMDs), else 4; the autotuner refines this by measurement
-    c->seg_rows = (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= 1024) ? 8 : 4;
-    c->nseg = (G.nth - 3) / c->seg_rows + 1;
+    set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= 1024) ? 8 : 4, 1);
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
@@ -282,9 +260,8 @@ int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
 
 int teuk_destroy(teuk_ctx* c) {
     if (c == nullptr) return TEUK_OK;
-    (void)hipStreamSynchronize(c->stream);
-    free_all(c);
-    delete c;
+    if (c->in_batch) return fail(TEUK_EINVAL, "context belongs to a batch; destroy the batch");
+    teuk_detail::destroy_ctx(c);
     return TEUK_OK;
 }
 
@@ -431,8 +408,11 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
     P.win_r = c->win_r;
     P.win_t = c->win_t;
     double2* wave = static_cast<double2*>(waveform);
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    while (k < nsteps) {
         const int64_t n = c->steps_done;
+        // a blocked launch takes k_steps iterations; the remainder runs singly
+        const int depth = (c->k_steps > 1 && nsteps - k >= c->k_steps) ? c->k_steps : 1;
         P.fh = P.fn = nullptr;
         P.org = nullptr;
         if (c->has_src) {
@@ -441,6 +421,11 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
             // the last iteration it supports is (nsamples - 2) / 2 (needs sample 2n + 1)
             const int64_t span = (c->nsamples - 2) / 2 - n + 1;
             if (int rc = ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
+            if (static_cast<int64_t>(slot) + depth > c->batch_len) {
+                // the block's iterations must share one batch: start a new one at n
+                c->batch_n0 = -1;
+                if (int rc = ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
+            }
             const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
@@ -451,6 +436,8 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
         P.phi_out = c->plane[c->cur ^ 1][0];
         P.pi_out = c->plane[c->cur ^ 1][1];
         P.wave = wave ? wave + k * G.nth : nullptr;
+        P.nstrips = (depth > 1) ? c->bstrips : c->nstrips;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
             if (c->ev_used == kTimingPool)
                 if (int rc = flush_timing(c)) return rc;
@@ -461,14 +448,18 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
                 c->ev_start.push_back(a);
                 c->ev_stop.push_back(b);
             }
-            HIP_TRY(teuk::launch_step(P, c->seg_rows, c->stream, c->ev_start[c->ev_used],
-                                      c->ev_stop[c->ev_used]), "step kernel");
+            e0 = c->ev_start[c->ev_used];
+            e1 = c->ev_stop[c->ev_used];
             c->ev_used += 1;
+        }
+        if (depth > 1) {
+            HIP_TRY(teuk::launch_block(P, c->seg_rows, depth, c->stream, e0, e1), "blocked step kernel");
         } else {
-            HIP_TRY(teuk::launch_step(P, c->seg_rows, c->stream), "step kernel");
+            HIP_TRY(teuk::launch_step(P, c->seg_rows, c->stream, e0, e1), "step kernel");
         }
         c->cur ^= 1;
-        c->steps_done += 1;
+        c->steps_done += depth;
+        k += depth;
     }
     return TEUK_OK;
 }
@@ -752,10 +743,13 @@ int teuk_extract_waveform(const teuk_ctx* c, void* out) {
 
 int teuk_set_tuning(teuk_ctx* c, const teuk_tuning* t) {
     if (int rc = check_ctx(c)) return rc;
-    if (t == nullptr || !teuk::valid_segment_rows(t->seg_rows))
-        return fail(TEUK_EINVAL, "seg_rows must be 4, 8 or 16");
-    c->seg_rows = t->seg_rows;
-    c->nseg = (c->G.nth - 3) / c->seg_rows + 1;
+    if (t == nullptr) return fail(TEUK_EINVAL, "null tuning");
+    if (t->k_steps == 1) {
+        if (!teuk::valid_segment_rows(t->seg_rows)) return fail(TEUK_EINVAL, "seg_rows must be 4, 8 or 16");
+    } else if (!teuk::valid_block(t->seg_rows, t->k_steps)) {
+        return fail(TEUK_EINVAL, "no blocked variant for this (seg_rows, k_steps); valid: (4,2), (8,2), (4,4)");
+    }
+    set_tuning_fields(c, t->seg_rows, t->k_steps);
     return TEUK_OK;
 }
 
@@ -763,6 +757,146 @@ int teuk_get_tuning(const teuk_ctx* c, teuk_tuning* out) {
     if (int rc = check_ctx(c)) return rc;
     if (out == nullptr) return fail(TEUK_EINVAL, "null output");
     out->seg_rows = c->seg_rows;
+    out->k_steps = c->k_steps;
+    return TEUK_OK;
+}
+
+int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
+                  int32_t* count) {
+    if (int rc = check_ctx(c)) return rc;
+    if (count != nullptr) *count = 0;
+    if (table != nullptr && capacity < 0) return fail(TEUK_EINVAL, "negative table capacity");
+    const Geometry& G = c->G;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "autotune device");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "autotune device properties");
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    char keybuf[256];
+    std::snprintf(keybuf, sizeof(keybuf), "%s nr=%d nth=%d kerr=%d ko=%d src=%s", arch.c_str(), G.nr, G.nth,
+                  G.a != 0.0 ? 1 : 0, c->ko_c != 0.0 ? 1 : 0, TEUK_SOURCE_HASH);
+    const std::string key = keybuf;
+
+    auto emit = [&](const std::vector<teuk_tune_entry>& v) {
+        int32_t w = 0;
+        if (table != nullptr)
+            for (const auto& e : v)
+                if (w < capacity) table[w++] = e;
+        if (count != nullptr) *count = w;
+    };
+
+    if (cache_path != nullptr) {
+        std::ifstream f(cache_path);
+        bool found = false;
+        teuk_tune_entry hit{};
+        std::string line;
+        while (f && std::getline(f, line)) {
+            std::istringstream ls(line);
+            std::string k, seg, kk, us;
+            if (!std::getline(ls, k, '\t') || !std::getline(ls, seg, '\t') || !std::getline(ls, kk, '\t') ||
+                !std::getline(ls, us, '\t'))
+                continue;
+            if (k != key) continue;
+            teuk_tune_entry e{};
+            e.seg_rows = std::atoi(seg.c_str());
+            e.k_steps = std::atoi(kk.c_str());
+            e.us_per_iteration = std::atof(us.c_str());
+            const bool ok = (e.k_steps == 1) ? teuk::valid_segment_rows(e.seg_rows)
+                                             : teuk::valid_block(e.seg_rows, e.k_steps);
+            if (ok) {
+                hit = e;
+                found = true;
+            }
+        }
+        if (found) {
+            set_tuning_fields(c, hit.seg_rows, hit.k_steps);
+            emit({hit});
+            return TEUK_OK;
+        }
+    }
+
+    std::vector<teuk_tune_entry> cand;
+    for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, 0.0});
+    for (const auto& v : teuk::kBlockVariants) cand.push_back({v.seg, v.k, 0.0});
+
+    // save what the trials disturb
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
+    const int cur0 = c->cur;
+    const int64_t steps0 = c->steps_done;
+    const bool src0 = c->has_src;
+    const bool timing0 = c->timing;
+    const int seg0 = c->seg_rows, k0 = c->k_steps;
+    double2* save[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (int rc = flush_timing(c)) return rc;
+    hipError_t e = hipMalloc(&save[0], plane_bytes);
+    if (e == hipSuccess) e = hipMalloc(&save[1], plane_bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(save[0]);
+        return fail(TEUK_ENOMEM, std::string("autotune planes: ") + hipGetErrorString(e));
+    }
+    auto restore = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        c->cur = cur0;
+        (void)hipMemcpyAsync(c->plane[cur0][0], save[0], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
+        (void)hipMemcpyAsync(c->plane[cur0][1], save[1], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        c->steps_done = steps0;
+        c->has_src = src0;
+        c->timing = timing0;
+        (void)hipFree(save[0]);
+        (void)hipFree(save[1]);
+        for (auto& x : ev)
+            if (x != nullptr) (void)hipEventDestroy(x);
+    };
+    e = hipMemcpyAsync(save[0], c->plane[cur0][0], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(save[1], c->plane[cur0][1], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        restore();
+        set_tuning_fields(c, seg0, k0);
+        return hip_fail(e, "autotune setup");
+    }
+    c->has_src = false;
+    c->timing = false;
+    constexpr int kWarm = 8, kIters = 32, kReps = 3;   // multiples of every blocked depth
+    for (auto& t : cand) {
+        set_tuning_fields(c, t.seg_rows, t.k_steps);
+        int rc = teuk_step_n(c, kWarm, nullptr);
+        double best = 1e300;
+        for (int r = 0; rc == TEUK_OK && r < kReps; ++r) {
+            float ms = 0.0f;
+            e = hipEventRecord(ev[0], c->stream);
+            if (e == hipSuccess) rc = teuk_step_n(c, kIters, nullptr);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventRecord(ev[1], c->stream);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess && rc == TEUK_OK) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess && rc == TEUK_OK) rc = hip_fail(e, "autotune timing");
+            best = std::min(best, 1e3 * static_cast<double>(ms) / kIters);
+        }
+        if (rc != TEUK_OK) {
+            const std::string msg = g_last_error;
+            restore();
+            set_tuning_fields(c, seg0, k0);
+            return fail(rc, msg);
+        }
+        t.us_per_iteration = best;
+    }
+    restore();
+    std::stable_sort(cand.begin(), cand.end(), [](const teuk_tune_entry& a, const teuk_tune_entry& b) {
+        return a.us_per_iteration < b.us_per_iteration;
+    });
+    set_tuning_fields(c, cand[0].seg_rows, cand[0].k_steps);
+    emit(cand);
+    if (cache_path != nullptr) {
+        std::ofstream f(cache_path, std::ios::app);
+        char line[512];
+        std::snprintf(line, sizeof(line), "%s\t%d\t%d\t%.4f\n", key.c_str(), cand[0].seg_rows, cand[0].k_steps,
+                      cand[0].us_per_iteration);
+        if (!(f << line)) return fail(TEUK_EINVAL, std::string("cannot append to tuning cache ") + cache_path);
+    }
     return TEUK_OK;
 }
 

@@ -1,0 +1,82 @@
+// Internal state of a context and the library's error helpers, shared by
+// the C ABI translation units (capi.cpp, batch.cpp).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/teuk.h"
+#include "geometry.h"
+
+namespace teuk_detail {
+
+extern thread_local std::string g_last_error;
+// Record msg as the calling thread's last error and return code.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// Release every device resource of a context and delete it (no ownership check).
+void destroy_ctx(teuk_ctx* c);
+
+}  // namespace teuk_detail
+
+#define HIP_TRY(expr, what)                                                  \
+    do {                                                                     \
+        hipError_t _e = (expr);                                              \
+        if (_e != hipSuccess) return teuk_detail::hip_fail(_e, what);        \
+    } while (0)
+
+struct teuk_ctx {
+    teuk::Geometry G;
+    bool in_batch = false;          // owned by a teuk_batch: teuk_destroy refuses it
+    hipStream_t stream = nullptr;
+    int ld = 0;
+    double2* plane[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [level][Phi, Pi]
+    int cur = 0;
+    double* d_rnode = nullptr;
+    double* d_rhalf = nullptr;
+    teuk::ThetaRow* d_rows = nullptr;
+    int* d_flag = nullptr;
+    double ko_c = 0.0;
+    int nstrips = 0, nseg = 0, seg_rows = 16;
+    int k_steps = 1;               // iterations per stencil launch (temporal blocking depth)
+    int bstrips = 0;               // strips of the blocked kernel at depth k_steps
+    int64_t steps_done = 0;
+    // source
+    bool has_src = false;
+    double amplitude = 0.0, sig_r = 0.0, sig_th = 0.0, cut = 0.0;
+    int64_t nsamples = 0;
+    double* d_orbit = nullptr;
+    int win_r = 0, win_t = 0;
+    double2* d_fh = nullptr;
+    double2* d_fn = nullptr;
+    int4* d_org = nullptr;
+    int64_t batch_n0 = -1;
+    int batch_len = 0;
+    double batch_amp = 0.0;
+    // adjoint
+    double2* adj[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int adj_cur = 0;
+    int64_t adj_clock = -1;
+    double* d_dA = nullptr;        // accumulated dL/dA (device)
+    double* d_dA_part = nullptr;   // per-wave partials of a run of adjoint iterations
+    int part_items = 0;            // partials per iteration (waves of the adjoint launch)
+    int part_filled = 0;           // iterations written since the last reduction
+    // checkpointed gradient
+    std::vector<double2*> snaps;   // 2 planes per snapshot: [2k] Phi, [2k+1] Pi
+    double2* seg_buf = nullptr;    // Phi on the loss rectangle, one slot per segment iteration
+    size_t seg_buf_bytes = 0;
+    double* d_ls = nullptr;        // accumulated sum |Phi|^2 over the rectangle
+    double* d_ls_part = nullptr;   // per-row partials (nth)
+    bool ckpt_valid = false;
+    teuk_grad_plan ckpt_plan{};
+    // kernel timing (measurement aid)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};

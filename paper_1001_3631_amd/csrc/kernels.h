@@ -10,6 +10,12 @@ namespace teuk {
 // Rows of theta per wave segment in the streaming stencil (compiled variants).
 constexpr int kSegVariants[] = {4, 8, 16};
 
+// Temporally blocked variants (theta rows per segment, iterations per launch).
+struct BlockVariant {
+    int seg, k;
+};
+constexpr BlockVariant kBlockVariants[] = {{4, 2}, {8, 2}, {4, 4}};
+
 struct StepParams {
     const double2* phi;         // u^n planes [nth][ld]
     const double2* pi;
@@ -29,6 +35,32 @@ struct StepParams {
     const double2* fn;          // nodes: [win_t][win_r]
     const int4* org;            // window origins: half (col0,row0), node (col0,row0)
     int win_r, win_t;
+};
+
+// One instance of a batched launch (homogeneous evolution; see lw_batch_kernel).
+struct BatchInstance {
+    double2* plane[2][2];       // [level][Phi, Pi], each [nth][ld]
+    const double* rnode;
+    const double* rhalf;
+    const ThetaRow* rows;
+    int nr, nth, ld, rpitch;
+    int nstrips, nseg;          // tiles of this instance: nstrips x nseg
+    double dt, inv_hr, ko_c;
+    int even, i_ext;
+    int cur;                    // level holding u at the launch's first iteration
+    int tile0;                  // index of tile (strip 0, segment 0) in the tile list
+    double2* wave;              // [rounds][nth] extraction rows, or null
+};
+
+struct BatchParams {
+    const BatchInstance* inst;
+    const int4* tiles;          // per tile: (instance, strip, segment, tile index)
+    int ntiles;                 // tiles per iteration (all instances)
+    int rounds;                 // iterations taken by this launch
+    unsigned long long* ticket; // work counter (zero at launch)
+    int* done;                  // per tile: iterations completed in this launch (zero at launch)
+    int* abort;                 // set to 1 when a dependency wait exceeds wait_limit
+    long long wait_limit;       // wall-clock ticks a dependency wait may take
 };
 
 struct SourceParams {
@@ -91,6 +123,12 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
                              int ld, hipStream_t stream);
 hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);
+bool valid_block(int seg, int k);
+int block_strip_width(int k);
+hipError_t launch_block(const StepParams& P, int seg, int k, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_stop = nullptr);
+hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream);
+hipError_t launch_batch(const BatchParams& B, int seg, int waves, hipStream_t stream);
 hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream);
 hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream);
 hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,

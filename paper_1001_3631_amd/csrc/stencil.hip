@@ -56,52 +56,74 @@ __device__ __forceinline__ int xcd_remap(int b, int nwg) {
 
 }  // namespace
 
-// One Lax-Wendroff iteration.  Each wave owns a strip of 64 columns (62
-// written, one halo column on each side) and a segment of theta rows, and
-// streams down the rows: load row jj of u^n, form the half-step row jj-1,
-// then the full-step row jj-2.  Radial neighbours come from the adjacent
-// lane; the theta window lives in registers (the loop is fully unrolled).
-template <int SEG>
-__global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
-    const int lane = threadIdx.x & 63;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int item = wg * 4 + (threadIdx.x >> 6);
-    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
-    const int strip = item / P.nseg;
-    const int seg = item - strip * P.nseg;
-    const int i = strip * 62 - 1 + lane;
-    const bool in_col = (i >= 0) && (i < P.nr);
-    const bool writer = in_col && lane >= 1 && lane <= 62;
-    const bool interior_col = (i >= 1) && (i <= P.nr - 2);
-    const int jlo = seg * SEG;
-    const int jhi = (seg == P.nseg - 1) ? P.nth : jlo + SEG;
+// One level of the streaming stencil: a wave owns 64 columns (lane = column,
+// column i = lane + offset) and produces the full-step rows [lo, hi) of one
+// Lax-Wendroff iteration, streaming down theta: load input row jj, form the
+// half-step row jj-1, then the full-step row jj-2.  Radial neighbours come
+// from the adjacent lane; the theta window lives in registers (the loop is
+// fully unrolled, NROW >= hi - lo).
+//
+// Input rows come from the planes P.phi/P.pi or (IN_LDS) from this wave's
+// LDS buffer; output rows go to P.phi_out/P.pi_out (owner lanes only) or
+// (OUT_LDS) back into the LDS buffer, every lane, in place: row r is read at
+// the iteration that loads it and written two iterations later.  Lanes
+// outside the grid read zeros and the Dirichlet columns are written as zero,
+// so a buffered level feeds the next exactly as a plane would.  Lanes whose
+// neighbours lie outside the wave produce values that no owner lane uses.
+struct LevelArgs {
+    int lo, hi;                    // full-step output rows of this level
+    int lane, i;
+    bool in_col, owner, interior_col;
+    const double2* fh;             // source windows of this iteration (or null)
+    const double2* fn;
+    int4 org;
+    double2* wave;                 // extraction row of this iteration (or null)
+    double2* lp;                   // LDS buffer of this wave: rows [lbase, ...) x 64 lanes
+    double2* lq;
+    int lbase;
+};
+
+template <int NROW, bool IN_LDS, bool OUT_LDS>
+__device__ __forceinline__ void stream_level(const StepParams& P, const LevelArgs& A, const RCol& rn,
+                                             const RCol& rh) {
     const int nth = P.nth;
     const int ld = P.ld;
-
-    int4 org = make_int4(0, 0, 0, 0);
-    if (P.org != nullptr) org = *P.org;
-    const int ic = min(max(i, 0), P.nr - 1);
-    const int ih = min(max(i, 0), P.nr - 2);
-    const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
-    const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
-
+    const int i = A.i;
+    const int lane = A.lane;
+    const int lo = A.lo, hi = A.hi;
     const double2 z = make_double2(0.0, 0.0);
-    double2 uP[SEG + 6], uQ[SEG + 6];     // u^n, own column, rows jlo-2+t
-    double2 sP[SEG + 6], sQ[SEG + 6], dP[SEG + 6], dQ[SEG + 6];
-    double2 hP[SEG + 6], hQ[SEG + 6];     // half-step values at i+1/2, rows jlo-2+t
-    double2 gP[SEG + 6], gQ[SEG + 6];     // half-step values at i-1/2 (from lane-1)
-    double2 oP1 = z, oQ1 = z;             // full-step row 1 (for the pole row 0)
-    double2 oPp = z, oQp = z;             // previous full-step row (for the last pole row)
+    double2 uP[NROW + 4], uQ[NROW + 4];     // input level, own column, rows lo-2+t
+    double2 sP[NROW + 4], sQ[NROW + 4], dP[NROW + 4], dQ[NROW + 4];
+    double2 hP[NROW + 4], hQ[NROW + 4];     // half-step values at i+1/2, rows lo-2+t
+    double2 gP[NROW + 4], gQ[NROW + 4];     // half-step values at i-1/2 (from lane-1)
+    double2 oP1 = z, oQ1 = z;               // full-step row 1 (for the pole row 0)
+    double2 oPp = z, oQp = z;               // previous full-step row (for the last pole row)
+
+    auto store = [&](int row, double2 vp, double2 vq) {
+        if (OUT_LDS) {
+            A.lp[(row - A.lbase) * 64 + lane] = vp;
+            A.lq[(row - A.lbase) * 64 + lane] = vq;
+        } else if (A.owner) {
+            P.phi_out[static_cast<size_t>(row) * ld + i] = vp;
+            P.pi_out[static_cast<size_t>(row) * ld + i] = vq;
+        }
+        if (A.wave != nullptr && A.owner && i == P.i_ext) A.wave[row] = vp;
+    };
 
 #pragma unroll
-    for (int t = 0; t < SEG + 6; ++t) {
-        const int jj = jlo - 2 + t;
-        if (jj <= jhi + 1) {
-            // ---- load row jj of u^n and form column sums/differences ----
+    for (int t = 0; t < NROW + 4; ++t) {
+        const int jj = lo - 2 + t;
+        if (jj <= hi + 1) {
+            // ---- load row jj of the input level and form column sums/differences ----
             double2 p = z, q = z;
-            if (jj >= 0 && jj < nth && in_col) {
-                p = P.phi[static_cast<size_t>(jj) * ld + i];
-                q = P.pi[static_cast<size_t>(jj) * ld + i];
+            if (jj >= 0 && jj < nth) {
+                if (IN_LDS) {
+                    p = A.lp[(jj - A.lbase) * 64 + lane];
+                    q = A.lq[(jj - A.lbase) * 64 + lane];
+                } else if (A.in_col) {
+                    p = P.phi[static_cast<size_t>(jj) * ld + i];
+                    q = P.pi[static_cast<size_t>(jj) * ld + i];
+                }
             }
             uP[t] = p;
             uQ[t] = q;
@@ -119,7 +141,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                 if (jh >= 1 && jh <= nth - 2) {
                     const ThetaRow R = P.rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2);
-                    const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
+                    const double2 F = src_lookup(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh);
                     lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
                              dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
                              c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
@@ -140,13 +162,13 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
             // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
             if (t >= 4) {
                 const int jf = jj - 2;
-                if (jf >= jlo && jf < jhi) {
+                if (jf >= lo && jf < hi) {
                     double2 oP = z, oQ = z;
                     const bool pole = (jf == 0) || (jf == nth - 1);
-                    if (!pole && interior_col) {
+                    if (!pole && A.interior_col) {
                         const ThetaRow R = P.rows[jf];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2);
-                        const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
+                        const double2 F = src_lookup(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf);
                         // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
                         const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
                         const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
@@ -168,29 +190,17 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                         }
                     }
                     if (!pole) {
-                        if (writer) {
-                            P.phi_out[static_cast<size_t>(jf) * ld + i] = oP;
-                            P.pi_out[static_cast<size_t>(jf) * ld + i] = oQ;
-                            if (P.wave != nullptr && i == P.i_ext) P.wave[jf] = oP;
-                        }
+                        store(jf, oP, oQ);
                         if (jf == 1) { oP1 = oP; oQ1 = oQ; }
-                        if (jf == 2) {   // pole row 0 from rows 1, 2
+                        if (jf == 2 && lo == 0) {   // pole row 0 from rows 1, 2
                             const double2 p0 = pole_value(P.even, oP1, oP);
                             const double2 q0 = pole_value(P.even, oQ1, oQ);
-                            if (writer) {
-                                P.phi_out[i] = interior_col ? p0 : z;
-                                P.pi_out[i] = interior_col ? q0 : z;
-                                if (P.wave != nullptr && i == P.i_ext) P.wave[0] = interior_col ? p0 : z;
-                            }
+                            store(0, A.interior_col ? p0 : z, A.interior_col ? q0 : z);
                         }
-                        if (jf == nth - 2) {   // last pole row from rows nth-2, nth-3
+                        if (jf == nth - 2 && hi == nth) {   // last pole row from rows nth-2, nth-3
                             const double2 pl = pole_value(P.even, oP, oPp);
                             const double2 ql = pole_value(P.even, oQ, oQp);
-                            if (writer) {
-                                P.phi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? pl : z;
-                                P.pi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? ql : z;
-                                if (P.wave != nullptr && i == P.i_ext) P.wave[nth - 1] = interior_col ? pl : z;
-                            }
+                            store(nth - 1, A.interior_col ? pl : z, A.interior_col ? ql : z);
                         }
                         oPp = oP;
                         oQp = oQ;
@@ -199,6 +209,216 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
             }
         }
     }
+}
+
+// One Lax-Wendroff iteration.  Work item = (strip of 62 output columns,
+// theta segment of SEG rows; the last segment takes up to SEG + 2).
+template <int SEG>
+__global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = wg * 4 + (threadIdx.x >> 6);
+    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
+    const int strip = item / P.nseg;
+    const int seg = item - strip * P.nseg;
+    LevelArgs A;
+    A.lane = threadIdx.x & 63;
+    A.i = strip * 62 - 1 + A.lane;
+    A.in_col = (A.i >= 0) && (A.i < P.nr);
+    A.owner = A.in_col && A.lane >= 1 && A.lane <= 62;
+    A.interior_col = (A.i >= 1) && (A.i <= P.nr - 2);
+    A.lo = seg * SEG;
+    A.hi = (seg == P.nseg - 1) ? P.nth : A.lo + SEG;
+    A.fh = P.fh;
+    A.fn = P.fn;
+    A.org = make_int4(0, 0, 0, 0);
+    if (P.org != nullptr) A.org = *P.org;
+    A.wave = P.wave;
+    A.lp = A.lq = nullptr;
+    A.lbase = 0;
+    const int ic = min(max(A.i, 0), P.nr - 1);
+    const int ih = min(max(A.i, 0), P.nr - 2);
+    const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+    const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+    stream_level<SEG + 2, false, false>(P, A, rn, rh);
+}
+
+// Temporal blocking: K consecutive iterations in one launch.  A work item is
+// one wave (a workgroup of 64 threads) on 64 columns and a theta segment.
+// Level l (1..K) produces rows [jlo - 2(K-l), jhi + 2(K-l)) clipped to the
+// grid: each iteration widens the dependence by 2 rows (the full step reads
+// u^n at j-2..j+2) and one column on each side, so the 64 lanes end with
+// 64 - 2K owner columns.  Levels 1..K-1 stay in this wave's LDS buffer; only
+// level K is written to HBM.  Every point goes through stream_level, so a
+// block is bitwise identical to K single iterations.
+template <int SEG, int K, int L>
+__device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, int jlo, int jhi,
+                                             const RCol& rn, const RCol& rh) {
+    constexpr int NROW = SEG + 2 + 4 * (K - L);
+    A.lo = max(0, jlo - 2 * (K - L));
+    A.hi = min(P.nth, jhi + 2 * (K - L));
+    const size_t wsz = static_cast<size_t>(P.win_r) * P.win_t;
+    A.fh = P.fh ? P.fh + (L - 1) * wsz : nullptr;
+    A.fn = P.fn ? P.fn + (L - 1) * wsz : nullptr;
+    A.org = make_int4(0, 0, 0, 0);
+    if (P.org != nullptr) A.org = P.org[L - 1];
+    A.wave = P.wave ? P.wave + static_cast<size_t>(L - 1) * P.nth : nullptr;
+    stream_level<NROW, (L > 1), (L < K)>(P, A, rn, rh);
+    if constexpr (L < K) block_levels<SEG, K, L + 1>(P, A, jlo, jhi, rn, rh);
+}
+
+template <int SEG, int K>
+__global__ void __launch_bounds__(64) lw_block_kernel(StepParams P) {
+    constexpr int ROWS = SEG + 2 + 4 * (K - 1);
+    __shared__ double2 bufP[ROWS * 64];
+    __shared__ double2 bufQ[ROWS * 64];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= P.nstrips * P.nseg) return;
+    const int strip = item / P.nseg;
+    const int seg = item - strip * P.nseg;
+    const int jlo = seg * SEG;
+    const int jhi = (seg == P.nseg - 1) ? P.nth : jlo + SEG;
+    LevelArgs A;
+    A.lane = threadIdx.x;
+    A.i = strip * (64 - 2 * K) - K + A.lane;
+    A.in_col = (A.i >= 0) && (A.i < P.nr);
+    A.owner = A.in_col && A.lane >= K && A.lane <= 63 - K;
+    A.interior_col = (A.i >= 1) && (A.i <= P.nr - 2);
+    A.lp = bufP;
+    A.lq = bufQ;
+    A.lbase = max(0, jlo - 2 * (K - 1));
+    const int ic = min(max(A.i, 0), P.nr - 1);
+    const int ih = min(max(A.i, 0), P.nr - 2);
+    const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+    const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+    block_levels<SEG, K, 1>(P, A, jlo, jhi, rn, rh);
+}
+
+// Batched persistent stepping: many independent instances (each its own
+// grid, coefficients and planes) advance `rounds` iterations in one launch.
+// Work item = one tile (instance, strip of 62 columns, theta segment) of one
+// iteration.  Each pass of a workgroup's loop takes four consecutive items
+// from a global counter (one per wave) in iteration-major order: every tile
+// of iteration n before any tile of n + 1.  The counter value and the abort
+// flag reach all threads through LDS between two workgroup barriers, so
+// every lane holds the same item without relying on lanes reconverging.
+//
+// Dependencies: the item (tile, n) reads u^n on its tile plus one column and
+// two rows of halo, all inside the 3 x 3 neighbourhood of tiles, and writes
+// the level that those tiles read at iteration n - 1.  It therefore waits
+// until each neighbour (itself included) has completed n iterations
+// (done >= n), then publishes done = n + 1.  Every wait is on an item with a
+// smaller ticket; a ticket is only handed out at the top of a pass and is
+// processed right away, so its holder is running and the smallest
+// unfinished ticket never waits: every wait ends.  A wait longer than
+// wait_limit (a broken invariant) sets *abort, and every workgroup leaves at
+// the top of its next pass.  Tile data is made visible across the XCDs' L2
+// caches by an agent-scope release after the tile's stores and an
+// agent-scope acquire after the wait.
+template <int SEG>
+__global__ void __launch_bounds__(256) lw_batch_kernel(BatchParams B) {
+    __shared__ unsigned long long s_base;
+    __shared__ int s_stop;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const unsigned long long total = static_cast<unsigned long long>(B.rounds) * B.ntiles;
+    while (true) {
+        __syncthreads();                     // the previous pass has read s_base / s_stop
+        if (threadIdx.x == 0) {
+            s_base = __hip_atomic_fetch_add(B.ticket, 4ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_stop = __hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const unsigned long long base = s_base;
+        if (s_stop != 0 || base >= total) break;          // the same decision in every thread
+        const unsigned long long tv = base + static_cast<unsigned long long>(wave);
+        // equal in every lane of the wave: move it to scalar registers
+        const unsigned long long t =
+            (static_cast<unsigned long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv >> 32))) << 32) |
+            static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv & 0xffffffffu)));
+        if (t >= total) continue;                          // this wave has no item in the last pass
+
+        const int n = static_cast<int>(t / static_cast<unsigned long long>(B.ntiles));
+        const int k = static_cast<int>(t - static_cast<unsigned long long>(n) * B.ntiles);
+        const int4 tile = B.tiles[k];
+        const BatchInstance& I = B.inst[tile.x];
+        const int strip = tile.y;
+        const int seg = tile.z;
+
+        if (n > 0 && lane < 9) {
+            const int s2 = strip + lane / 3 - 1;
+            const int q2 = seg + lane % 3 - 1;
+            if (s2 >= 0 && s2 < I.nstrips && q2 >= 0 && q2 < I.nseg) {
+                const int* f = B.done + I.tile0 + s2 * I.nseg + q2;
+                const long long t0 = wall_clock64();
+                while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
+                    if (__hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                    if (wall_clock64() - t0 > B.wait_limit) {
+                        __hip_atomic_store(B.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        // after an abort the item is still computed (on whatever data is
+        // there); the host reports the abort and the states are invalid
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        StepParams P;
+        const int lv = (I.cur + n) & 1;
+        P.phi = I.plane[lv][0];
+        P.pi = I.plane[lv][1];
+        P.phi_out = I.plane[lv ^ 1][0];
+        P.pi_out = I.plane[lv ^ 1][1];
+        P.rnode = I.rnode;
+        P.rhalf = I.rhalf;
+        P.rows = I.rows;
+        P.nr = I.nr;
+        P.nth = I.nth;
+        P.ld = I.ld;
+        P.rpitch = I.rpitch;
+        P.nstrips = I.nstrips;
+        P.nseg = I.nseg;
+        P.dt = I.dt;
+        P.inv_hr = I.inv_hr;
+        P.ko_c = I.ko_c;
+        P.even = I.even;
+        P.i_ext = I.i_ext;
+        P.wave = nullptr;
+        P.fh = P.fn = nullptr;
+        P.org = nullptr;
+        P.win_r = P.win_t = 0;
+        LevelArgs A;
+        A.lane = lane;
+        A.i = strip * 62 - 1 + lane;
+        A.in_col = (A.i >= 0) && (A.i < P.nr);
+        A.owner = A.in_col && lane >= 1 && lane <= 62;
+        A.interior_col = (A.i >= 1) && (A.i <= P.nr - 2);
+        A.lo = seg * SEG;
+        A.hi = (seg == P.nseg - 1) ? P.nth : A.lo + SEG;
+        A.fh = A.fn = nullptr;
+        A.org = make_int4(0, 0, 0, 0);
+        A.wave = I.wave ? I.wave + static_cast<size_t>(n) * P.nth : nullptr;
+        A.lp = A.lq = nullptr;
+        A.lbase = 0;
+        const int ic = min(max(A.i, 0), P.nr - 1);
+        const int ih = min(max(A.i, 0), P.nr - 2);
+        const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+        const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+        stream_level<SEG + 2, false, false>(P, A, rn, rh);
+
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(B.done + tile.w, n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Zero the work counter and the per-tile counters (a kernel, so that it can
+// be a node of a captured graph).  The abort flag is left alone: once set, it
+// stays set (and later launches exit at once) until the host has read it.
+__global__ void __launch_bounds__(256) batch_reset_kernel(BatchParams B) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *B.ticket = 0ull;
+    if (e < B.ntiles) B.done[e] = 0;
 }
 
 // Compact source pass: F on the windows near the particle for a batch of
@@ -313,6 +533,49 @@ hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEven
         case 4: hipExtLaunchKernelGGL(lw_step_kernel<4>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
         case 8: hipExtLaunchKernelGGL(lw_step_kernel<8>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
         case 16: hipExtLaunchKernelGGL(lw_step_kernel<16>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool valid_block(int seg, int k) {
+    for (const auto& v : kBlockVariants)
+        if (v.seg == seg && v.k == k) return true;
+    return false;
+}
+
+int block_strip_width(int k) { return 64 - 2 * k; }
+
+// P.nstrips = ceil(nr / (64 - 2k)), P.nseg as for launch_step; P.fh, P.fn,
+// P.org point at the windows of the block's first iteration (the next k - 1
+// follow at strides win_r * win_t and 1), P.wave at k rows of nth.
+hipError_t launch_block(const StepParams& P, int seg, int k, hipStream_t stream, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+    const dim3 grid(P.nstrips * P.nseg), block(64);
+    if (seg == 4 && k == 2)
+        hipExtLaunchKernelGGL((lw_block_kernel<4, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+    else if (seg == 8 && k == 2)
+        hipExtLaunchKernelGGL((lw_block_kernel<8, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+    else if (seg == 4 && k == 4)
+        hipExtLaunchKernelGGL((lw_block_kernel<4, 4>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((B.ntiles + 255) / 256), dim3(256), 0, stream, B);
+    return hipGetLastError();
+}
+
+// waves = persistent waves to start (4 per workgroup); every wave loops over
+// the work counter, so any positive number is correct.
+hipError_t launch_batch(const BatchParams& B, int seg, int waves, hipStream_t stream) {
+    const dim3 grid((waves + 3) / 4), block(256);
+    switch (seg) {
+        case 4: hipLaunchKernelGGL(lw_batch_kernel<4>, grid, block, 0, stream, B); break;
+        case 8: hipLaunchKernelGGL(lw_batch_kernel<8>, grid, block, 0, stream, B); break;
+        case 16: hipLaunchKernelGGL(lw_batch_kernel<16>, grid, block, 0, stream, B); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -7,6 +7,7 @@ the current HIP device.
 """
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -49,12 +50,28 @@ class Engine:
         self._orbit = None
         self._gw = None
 
+    @classmethod
+    def _borrowed(cls, lib, ctx, m, stream):
+        """View of a context owned elsewhere (a batch instance); close() is a no-op."""
+        e = cls.__new__(cls)
+        e._lib = lib
+        e.stream = stream
+        e.ctx = ctx
+        e.m = int(m)
+        e._orbit = None
+        e._gw = None
+        e._borrowed_ctx = True
+        return e
+
     @property
     def has_source(self):
         return self._orbit is not None
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
+        if getattr(self, "_borrowed_ctx", False):
+            self.ctx = None
+            return
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self._lib.teuk_destroy(self.ctx)
             self.ctx = None
@@ -143,11 +160,23 @@ class Engine:
     def tuning(self):
         t = L.Tuning()
         L.check(self._lib.teuk_get_tuning(self.ctx, ctypes.byref(t)))
-        return {"seg_rows": t.seg_rows}
+        return {"seg_rows": t.seg_rows, "k_steps": t.k_steps}
 
-    def set_tuning(self, seg_rows):
-        t = L.Tuning(int(seg_rows))
+    def set_tuning(self, seg_rows, k_steps=1):
+        """Launch configuration: theta rows per segment and iterations per launch."""
+        t = L.Tuning(int(seg_rows), int(k_steps))
         L.check(self._lib.teuk_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def autotune(self, cache_path=None):
+        """Measure every launch configuration (or take it from the cache file)
+        and keep the fastest; returns [(seg_rows, k_steps, us/iteration)],
+        fastest first (one entry when served from the cache)."""
+        cap = 16
+        table = (L.TuneEntry * cap)()
+        n = ctypes.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        L.check(self._lib.teuk_autotune(self.ctx, path, table, cap, ctypes.byref(n)))
+        return [(table[k].seg_rows, table[k].k_steps, table[k].us_per_iteration) for k in range(n.value)]
 
     # -- adjoint ------------------------------------------------------------
     def adjoint_begin(self, n_end, lam_phi=None, lam_pi=None, gw=None):
@@ -227,3 +256,80 @@ class Engine:
 
     def check_finite(self):
         L.check(self._lib.teuk_check_finite(self.ctx))
+
+
+class Batch:
+    """Many independent instances stepped by one persistent launch (teuk_batch_*).
+
+    grids: list of dicts with Engine's grid parameters.  instances[k] is an
+    Engine view of instance k (set_state, init_pulse, get_state, ...)."""
+
+    def __init__(self, grids, stream=None):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the engine needs a HIP device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        n = len(grids)
+        descs = (L.GridDesc * n)()
+        for k, g in enumerate(grids):
+            descs[k] = L.GridDesc(float(g["M"]), float(g["a"]), int(g["s"]), int(g["m"]), int(g["nr"]),
+                                  int(g["nth"]), float(g["rs_min"]), float(g["rs_max"]), float(g.get("cfl", 0.5)),
+                                  float(g.get("rs_extract", g["rs_max"])), float(g.get("ko_eps", 0.5)))
+        ctx = ctypes.c_void_p()
+        L.check(self._lib.teuk_batch_create(n, descs, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.instances = []
+        for k, g in enumerate(grids):
+            ic = ctypes.c_void_p()
+            L.check(self._lib.teuk_batch_instance(self.ctx, k, ctypes.byref(ic)))
+            self.instances.append(Engine._borrowed(self._lib, ic, g["m"], self.stream))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            for e in self.instances:
+                e.close()
+            self._lib.teuk_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def seg_rows(self):
+        v = ctypes.c_int32()
+        L.check(self._lib.teuk_batch_get_tuning(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_tuning(self, seg_rows):
+        L.check(self._lib.teuk_batch_set_tuning(self.ctx, int(seg_rows)))
+
+    def step(self, nsteps, waveform=True, out=None):
+        """nsteps iterations of every instance; returns the per-instance
+        (nsteps, nth) waveforms (out, if given), or None."""
+        n = len(self.instances)
+        ws = None
+        arr = None
+        if waveform:
+            if out is None:
+                out = [torch.empty((int(nsteps), e.shape[0]), dtype=torch.complex128, device="cuda")
+                       for e in self.instances]
+            for t, e in zip(out, self.instances):
+                _need_device(t, (int(nsteps), e.shape[0]), "waveform")
+            ws = list(out)
+            arr = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ws])
+        L.check(self._lib.teuk_batch_step_n(self.ctx, int(nsteps), arr))
+        return ws
+
+    def sync(self):
+        L.check(self._lib.teuk_batch_sync(self.ctx))
+
+    def autotune(self, cache_path=None):
+        cap = 8
+        table = (L.TuneEntry * cap)()
+        cnt = ctypes.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        L.check(self._lib.teuk_batch_autotune(self.ctx, path, table, cap, ctypes.byref(cnt)))
+        return [(table[k].seg_rows, table[k].k_steps, table[k].us_per_iteration) for k in range(cnt.value)]

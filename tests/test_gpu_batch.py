@@ -1,0 +1,167 @@
+"""Batched persistent stepping through the C ABI.
+
+Each instance of a batch must end bitwise equal to the same instance stepped
+alone with teuk_step_n (same per-point device code): states and waveform rows,
+for heterogeneous instances (a, m, s, grid shapes down to nr = 5, nth = 7,
+dissipation on and off), for repeated launches of a cached graph, for a new
+iteration count (new graph), and for every segment length.  One instance is
+also checked against the oracle directly, and the batched workload's real
+shapes are covered by a subset of its instances.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import teuk_oracle as T
+from paper_1001_3631_amd import workloads as W
+
+from test_gpu_parity import STEP_GRIDS, gpu_engine, host, rel, to_dev
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1001_3631_amd import _lib
+    _lib.load()
+
+
+def make_batch(grids):
+    from paper_1001_3631_amd.engine import Batch
+    return Batch(grids)
+
+
+def single_runs(grids, states, plan):
+    """Each instance alone: plan = list of iteration counts run back to back."""
+    out = []
+    for g, (phi, pi) in zip(grids, states):
+        eng = gpu_engine(g)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        ws = [host(eng.step(n)) for n in plan]
+        p, q = eng.get_state()
+        out.append((np.concatenate(ws), host(p), host(q)))
+        eng.close()
+    return out
+
+
+def batch_runs(grids, states, plan, seg=None):
+    b = make_batch(grids)
+    if seg is not None:
+        b.set_tuning(seg)
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    ws = [[] for _ in grids]
+    for n in plan:
+        w = b.step(n)
+        for k in range(len(grids)):
+            ws[k].append(host(w[k]))
+    b.sync()
+    out = []
+    for k, e in enumerate(b.instances):
+        p, q = e.get_state()
+        out.append((np.concatenate(ws[k]), host(p), host(q)))
+        assert e.info["steps_done"] == sum(plan)
+    b.close()
+    return out
+
+
+def assert_bitwise(a, b):
+    for x, y in zip(a, b):
+        assert x.shape == y.shape
+        assert np.array_equal(x, y), float(np.max(np.abs(x - y)))
+
+
+MIXED = STEP_GRIDS + [
+    dict(M=1.0, a=0.5, s=-1, m=3, nr=77, nth=33, rs_min=-30.0, rs_max=50.0, cfl=0.5, rs_extract=5.0, ko_eps=0.5),
+]
+
+
+@pytest.mark.parametrize("seg", [4, 8, 16])
+def test_batch_bitwise_equal_to_single_instances(seg):
+    states = [W.random_state(g["nth"], g["nr"], seed=31 + k) for k, g in enumerate(MIXED)]
+    plan = [5, 5, 3]            # a cached graph replayed, then a new iteration count
+    ref = single_runs(MIXED, states, plan)
+    got = batch_runs(MIXED, states, plan, seg=seg)
+    for a, b in zip(got, ref):
+        assert_bitwise(a, b)
+
+
+def test_batch_instance_against_oracle():
+    grids = MIXED[:3]
+    states = [W.random_state(g["nth"], g["nr"], seed=41 + k) for k, g in enumerate(grids)]
+    got = batch_runs(grids, states, [4])
+    for g_d, (phi, pi), (w, p, q) in zip(grids, states, got):
+        g = T.Grid(**g_d)
+        rp, rq = phi, pi
+        rw = []
+        for n in range(4):
+            rp, rq = T.step(g, rp, rq, n, None)
+            rw.append(rp[:, g.i_ext])
+        assert rel(p, rp) <= 1e-13
+        assert rel(q, rq) <= 1e-13
+        assert rel(w, np.array(rw)) <= 1e-13
+
+
+def test_batched_workload_subset_bitwise():
+    """Instances of the batched workload at their real sizes (one of each grid
+    level), Gaussian pulses, 12 iterations."""
+    inst = W.batched_instances()
+    pick = []
+    for lvl in range(4):
+        for it in inst:
+            if it["grid"]["nth"] == 32 * 2 ** lvl:
+                pick.append(it)
+                break
+    grids = [it["grid"] for it in pick]
+    b = make_batch(grids)
+    for e, it in zip(b.instances, pick):
+        e.init_pulse(**it["pulse"])
+    ws = b.step(12)
+    b.sync()
+    got = [(host(w),) + tuple(host(x) for x in e.get_state()) for w, e in zip(ws, b.instances)]
+    b.close()
+    for it, g_out in zip(pick, got):
+        eng = gpu_engine(it["grid"])
+        eng.init_pulse(**it["pulse"])
+        w = host(eng.step(12))
+        p, q = eng.get_state()
+        assert_bitwise(g_out, (w, host(p), host(q)))
+        assert np.max(np.abs(g_out[1])) > 0.0
+        eng.close()
+
+
+def test_batch_rejects_sources_and_bad_arguments():
+    from paper_1001_3631_amd._lib import TeukError
+    grids = MIXED[:2]
+    b = make_batch(grids)
+    with pytest.raises(TeukError):
+        b.set_tuning(12)
+    e = b.instances[0]
+    orbit = e.orbit_circular(10.0, 9, M=1.0, a=grids[0]["a"])
+    e.set_source(orbit, 1.0, 2.0, 2.0, 8.0)
+    with pytest.raises(TeukError):
+        b.step(2)
+    assert e._lib.teuk_destroy(e.ctx) == -1        # TEUK_EINVAL: owned by the batch
+    b.close()
+
+
+def test_batch_autotune_restores_states(tmp_path):
+    grids = MIXED[:4]
+    states = [W.random_state(g["nth"], g["nr"], seed=51 + k) for k, g in enumerate(grids)]
+    b = make_batch(grids)
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    b.step(3, waveform=False)
+    before = [tuple(host(x) for x in e.get_state()) for e in b.instances]
+    table = b.autotune(str(tmp_path / "tune.txt"))
+    assert {s for s, _, _ in table} == {4, 8, 16}
+    assert b.seg_rows == table[0][0]
+    for e, st in zip(b.instances, before):
+        assert_bitwise(tuple(host(x) for x in e.get_state()), st)
+        assert e.info["steps_done"] == 3
+    hit = b.autotune(str(tmp_path / "tune.txt"))
+    assert len(hit) == 1 and hit[0][0] == table[0][0]
+    b.close()
