@@ -261,11 +261,12 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
 /* Batched stepping: many independent instances (each its own M, a, s, m,
  * grid and state) advanced together by ONE persistent kernel launch,
  * captured in a HIP graph together with a small kernel that resets its work
- * counters.  Work items are tiles (instance, strip of 62 r* columns, theta
- * segment of seg_rows rows) of one iteration; persistent waves take them from
- * a global counter in iteration-major order, and each item waits on per-tile
- * completion counters of its neighbouring tiles (the iteration's data
- * dependences, Sec. 3.2 half and full steps) instead of a launch boundary.
+ * counters.  Work items are tiles (instance, strip of 62 r* columns over all
+ * theta rows, walked in segments of seg_rows rows) of one iteration;
+ * persistent waves take them from a global counter in iteration-major order,
+ * and each item waits on per-tile completion counters of its neighbouring
+ * strips (the iteration's data dependences, Sec. 3.2 half and full steps)
+ * instead of a launch boundary.
  * Every point is evaluated by the same device code as teuk_step_n, so an
  * instance's results are bitwise equal to stepping it alone.
  *
@@ -276,8 +277,7 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  *   teuk_set_state / teuk_init_pulse / teuk_get_state / teuk_step_n / ...;
  *   teuk_destroy refuses it (EINVAL), teuk_batch_destroy frees it.
  * teuk_batch_set_tuning / get_tuning: theta rows per segment, 4, 8 or 16
- *   (EINVAL otherwise); synchronizes.  The default is chosen from the
- *   batch's total tile count at creation.
+ *   (EINVAL otherwise); synchronizes.  The default is 16.
  * teuk_batch_step_n: nsteps (0 <= nsteps <= INT32_MAX) iterations of every
  *   instance.  waveforms = NULL or a host array of n device pointers, each
  *   NULL or nsteps * nth complex128 (the extraction column after every

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
             nQ[k] = nD[k] = nDQ[k] = nC[k] = nW[k] = cz();
             if (interior_row && interior_col) {
                 const ThetaRow R = P.rows[r];
-                const Coef c = coef_at(rn, R.cos_th, R.sin2);
+                const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi' = Phi + dt (Pi~ - b dPhi);  Pi' = Pi + dt (b dPi + S),
                 // S = -c_t Pi~ + m_r dPhi + C_0 Phi~ + w Ang[Phi~] + F
                 const double2 ctq = cmul_conj(c.ct, q);
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
                     if (r2 == nth - 3) { p = axpy(-third, hP[k + 2], p); q = axpy(-third, hQ[k + 2], q); }
                 }
                 const ThetaRow R = P.rows[r2];
-                const Coef c = coef_at(rh, R.cos_th, R.sin2);
+                const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi^h = Phi~ + hdt (Pi~ - b dPhi);  Pi^h = Pi~ + hdt (b dPi + S)
                 yW[k] = make_double2(hdt * c.w * q.x, hdt * c.w * q.y);
                 const double2 c0q = cmul_conj(c.c0, q);

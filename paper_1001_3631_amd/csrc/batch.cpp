@@ -60,9 +60,10 @@ struct teuk_batch {
 
 namespace {
 
-int tiles_for(const teuk_batch* b, int seg) {
+// One tile per strip of 62 columns of each instance.
+int tiles_for(const teuk_batch* b) {
     long total = 0;
-    for (const teuk_ctx* c : b->inst) total += static_cast<long>(c->nstrips) * ((c->G.nth - 3) / seg + 1);
+    for (const teuk_ctx* c : b->inst) total += c->nstrips;
     return total > INT_MAX ? -1 : static_cast<int>(total);
 }
 
@@ -92,17 +93,16 @@ void free_batch(teuk_batch* b) {
     delete b;
 }
 
-// Tile list for a segment length: instance-major, then strip, then segment;
-// tile index = position in the list (also the index of its done counter).
+// Tile list: instance-major, then strip; tile index = position in the list
+// (also the index of its done counter).  The segment length only changes
+// how each wave walks its strip.
 int set_batch_tiles(teuk_batch* b, int seg) {
     std::vector<int4> tiles;
     tiles.reserve(b->max_tiles);
     for (size_t k = 0; k < b->inst.size(); ++k) {
         teuk_ctx* c = b->inst[k];
-        const int nseg = (c->G.nth - 3) / seg + 1;
         for (int s = 0; s < c->nstrips; ++s)
-            for (int q = 0; q < nseg; ++q)
-                tiles.push_back(make_int4(static_cast<int>(k), s, q, static_cast<int>(tiles.size())));
+            tiles.push_back(make_int4(static_cast<int>(k), s, 0, static_cast<int>(tiles.size())));
     }
     HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice),
             "batch tiles");
@@ -140,11 +140,12 @@ int upload_instances(teuk_batch* b, void* const* waveforms) {
         I.inv_hr = 1.0 / G.h_r;
         I.ko_c = c->ko_c;
         I.even = (std::abs(G.m) % 2 == 0);
+        I.kerr = (G.a != 0.0);
         I.i_ext = G.i_ext;
         I.cur = c->cur;
         I.tile0 = tile0;
         I.wave = waveforms ? static_cast<double2*>(waveforms[j]) : nullptr;
-        tile0 += I.nstrips * I.nseg;
+        tile0 += I.nstrips;
     }
     HIP_TRY(hipMemcpyAsync(b->d_inst, h, sizeof(teuk::BatchInstance) * b->inst.size(), hipMemcpyHostToDevice,
                            b->stream),
@@ -223,7 +224,7 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, 
         c->in_batch = true;
         b->inst.push_back(c);
     }
-    b->max_tiles = tiles_for(b, 4);
+    b->max_tiles = tiles_for(b);
     if (b->max_tiles < 0) {
         free_batch(b);
         return fail(TEUK_EINVAL, "too many tiles in one batch");
@@ -250,8 +251,7 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, 
     }
     b->resident_waves = 8 * std::max(cus, 1);
     b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * std::max(khz, 1));
-    // default segment: the single-instance rule applied to the whole batch
-    const int seg = (static_cast<long>(tiles_for(b, 8)) >= 1024) ? 8 : 4;
+    const int seg = 16;   // each wave walks a whole strip: long segments, fewest halo rows
     if (int rc = set_batch_tiles(b, seg)) {
         const std::string msg = teuk_detail::g_last_error;
         free_batch(b);

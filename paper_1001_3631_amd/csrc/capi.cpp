@@ -323,6 +323,7 @@ int teuk_init_pulse(teuk_ctx* c, double center, double width, double amplitude) 
     Q.width = width;
     Q.amplitude = amplitude;
     Q.even = (std::abs(c->G.m) % 2 == 0);
+    Q.kerr = (c->G.a != 0.0);
     HIP_TRY(teuk::launch_init_pulse(Q, c->stream), "init_pulse");
     c->steps_done = 0;
     c->batch_n0 = -1;
@@ -404,6 +405,7 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
     P.inv_hr = 1.0 / G.h_r;
     P.ko_c = c->ko_c;
     P.even = (std::abs(G.m) % 2 == 0);
+    P.kerr = (G.a != 0.0);
     P.i_ext = G.i_ext;
     P.win_r = c->win_r;
     P.win_t = c->win_t;
@@ -529,6 +531,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.inv_hr = 1.0 / G.h_r;
     P.ko_c = c->ko_c;
     P.even = (std::abs(G.m) % 2 == 0);
+    P.kerr = (G.a != 0.0);
     P.i_ext = G.i_ext;
     P.win_r = c->win_r;
     P.win_t = c->win_t;

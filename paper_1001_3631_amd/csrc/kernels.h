@@ -28,6 +28,7 @@ struct StepParams {
     int nstrips, nseg;          // work decomposition: strips of 62 columns x theta segments
     double dt, inv_hr, ko_c;    // ko_c = ko_eps / 16
     int even;                   // |m| even: Neumann poles, else Dirichlet
+    int kerr;                   // a != 0
     int i_ext;
     double2* wave;              // nth entries for this iteration, or null
     // source windows of this iteration (null when no source)
@@ -44,17 +45,17 @@ struct BatchInstance {
     const double* rhalf;
     const ThetaRow* rows;
     int nr, nth, ld, rpitch;
-    int nstrips, nseg;          // tiles of this instance: nstrips x nseg
+    int nstrips, nseg;          // tiles (strips) of this instance; theta segments per strip
     double dt, inv_hr, ko_c;
-    int even, i_ext;
+    int even, kerr, i_ext;
     int cur;                    // level holding u at the launch's first iteration
-    int tile0;                  // index of tile (strip 0, segment 0) in the tile list
+    int tile0;                  // index of its strip 0 in the tile list
     double2* wave;              // [rounds][nth] extraction rows, or null
 };
 
 struct BatchParams {
     const BatchInstance* inst;
-    const int4* tiles;          // per tile: (instance, strip, segment, tile index)
+    const int4* tiles;          // per tile: (instance, strip, 0, tile index)
     int ntiles;                 // tiles per iteration (all instances)
     int rounds;                 // iterations taken by this launch
     unsigned long long* ticket; // work counter (zero at launch)
@@ -86,7 +87,7 @@ struct PulseParams {
     const double* rnode_rs;
     const ThetaRow* rows;
     double center, width, amplitude;
-    int even;
+    int even, kerr;
 };
 
 struct AdjointParams {
@@ -100,7 +101,7 @@ struct AdjointParams {
     int nr, nth, ld, rpitch;
     int nstrips, nseg;
     double dt, inv_hr, ko_c;
-    int even;
+    int even, kerr;
     int i_ext;
     const double2* gw;          // dL/dw_n to inject at column i_ext after the step (nth), or null
     const double2* fh;          // unit-amplitude source windows of the forward iteration n

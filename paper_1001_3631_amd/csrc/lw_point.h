@@ -43,8 +43,10 @@ struct Coef {
 // b = q g, w = Delta g^2, c_t, C_0 = numerators g^2, g = 1/Sigma,
 // Re m_r = [mr_p - a^2 Delta sin^2 (mr_k1/(q + Sigma) + mr_k2)] g^4,
 // Im m_r = b Im c_t + mr_b g^2.  For a = 0 the bracket's second term is zero
-// and the division is skipped.
-__device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin2) {
+// and the division is skipped; kerr (a != 0) is the same for every point of
+// a grid, so the test is a uniform branch.  (Where a^2 Delta is 0 with
+// a != 0 the term is an exact signed zero, so both forms agree bitwise.)
+__device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin2, bool kerr) {
     const double sig2 = fma(-r.a2d, sin2, r.q2);
     const double g = rsqrt(sig2);
     const double g2 = g * g;
@@ -57,7 +59,7 @@ __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin
     c.c0.x = r.c0_re * g2;
     c.c0.y = r.c0_im * g2;
     double num = r.mr_p;
-    if (r.a2d != 0.0) {
+    if (kerr) {
         const double inv_qs = 1.0 / fma(sig2, g, r.q);   // 1/(q + Sigma), Sigma = Sigma^2 g
         num = fma(-r.a2d * sin2, fma(r.mr_k1, inv_qs, r.mr_k2), num);
     }
