@@ -7,10 +7,11 @@ waveform extracted at r* = 500M after every iteration, from zero data in HBM.
 value = grid-point updates per second (GPts/s) over the timed steps.
 
 Also reported on the same JSON line:
-  roofline      dominant kernel (the stencil): algorithmic HBM bytes per
-                launch (64 B per point: read and write Phi, Pi) over its
-                average launch duration, from HIP events around every
-                stencil launch of one extra evolution;
+  roofline      dominant kernel (the stencil, in the launch configuration
+                the autotuner picks before timing): algorithmic HBM bytes per
+                launch (64 B per point: read u^n and write u^{n+k}, Phi and
+                Pi) over its average launch duration, from HIP events around
+                every stencil launch of one extra evolution;
   hbm_grid      the same physics on 12800 x 256 (larger than the last-level
                 cache), GPts/s and algorithmic GB/s;
   batched       64 independent instances of uneven size (seeded m, a, grid
@@ -35,7 +36,7 @@ BYTES_PER_POINT = 64.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kernel_kerr_emri_6400x128_traffic.json")
 
 
-def measured_traffic(seg_rows):
+def measured_traffic(seg_rows, k_steps):
     """HBM-side bytes per stencil launch from the committed counter summary,
     or None if the stencil sources or the launch configuration changed since."""
     import hashlib
@@ -46,7 +47,7 @@ def measured_traffic(seg_rows):
     h = hashlib.sha256()
     for src in rec["kernel_sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    if h.hexdigest() != rec["sources_sha256"] or f"seg_rows {seg_rows}" not in rec["workload"]:
+    if h.hexdigest() != rec["sources_sha256"] or rec.get("tuning") != [seg_rows, k_steps]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -64,6 +65,8 @@ def parse():
     ap.add_argument("--batched-iterations", type=int, default=10000)
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
+    ap.add_argument("--tuning", default=None,
+                    help="SEG,K: fixed launch configuration instead of the autotuner (profiling passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -110,6 +113,7 @@ def adjoint_ratio(args):
     g = cfg["grid"]
     n = cfg["steps"]
     eng = make_engine(cfg, n)
+    eng.autotune(None)                      # the forward at its best launch configuration
     y = torch.zeros((n, g["nth"]), dtype=torch.complex128, device="cuda")
 
     def timed(fn):
@@ -141,8 +145,10 @@ def adjoint_ratio(args):
         return eng.backward_checkpointed(gw, 0.0)
 
     tc, _ = timed(ckpt)
+    tune = eng.tuning
     eng.close()
-    return {"workload": cfg["name"], "iterations": n, "forward_s": round(tf, 4), "adjoint_s": round(ta, 4),
+    return {"workload": cfg["name"], "iterations": n, "tuning": tune,
+            "forward_s": round(tf, 4), "adjoint_s": round(ta, 4),
             "ratio": round(ta / tf, 3), "forward_plus_backward_with_recompute_s": round(tc, 4),
             "ratio_with_recompute": round((tc - tf) / tf, 3)}
 
@@ -232,6 +238,12 @@ def main():
     n = args.iterations or cfg["steps"]
     npts = g["nr"] * g["nth"]
     eng = make_engine(cfg, n)
+    if args.tuning:
+        seg, k = (int(v) for v in args.tuning.split(","))
+        eng.set_tuning(seg, k)
+    else:
+        eng.autotune(None)                  # launch configuration by measurement (untimed)
+    tune = eng.tuning
     zphi = torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda")
     zpi = torch.zeros_like(zphi)
     wave = torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda")
@@ -259,8 +271,9 @@ def main():
     achieved = npts * BYTES_PER_POINT / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(eng.tuning["seg_rows"]),
-                "kernel": "lw_step_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
+                "traffic": measured_traffic(tune["seg_rows"], tune["k_steps"]),
+                "kernel": "lw_step_kernel" if tune["k_steps"] == 1 else "lw_block_kernel",
+                "avg_launch_us": round(avg_s * 1e6, 3),
                 "bytes_per_launch": int(npts * BYTES_PER_POINT), "launches_timed": kn}
     print(f"[bench] stencil launch avg {avg_s*1e6:.2f} us -> {achieved:.0f} GB/s algorithmic",
           file=sys.stderr, flush=True)
@@ -313,7 +326,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [g["nr"], g["nth"]], "iterations": n,
                    "a": g["a"], "m": g["m"], "s": g["s"], "source": "circular r0=10M",
-                   "extraction": "every iteration at r*=500M", "parallelism": "single GPU"},
+                   "extraction": "every iteration at r*=500M", "parallelism": "single GPU",
+                   "tuning": {"seg_rows": tune["seg_rows"], "k_steps": tune["k_steps"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -270,13 +270,34 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
     }
 }
 
-// Sum the per-wave partials of one launch into acc[slot] (single wave, fixed order).
-__global__ void __launch_bounds__(64) reduce_partials_kernel(const double* __restrict__ part, int n,
-                                                             double* __restrict__ acc) {
+// Sum n per-wave partials into *acc in a fixed order (the result depends only
+// on the partials and n): block b sums the chunk [4096 b, 4096 (b + 1)), each
+// thread 16 consecutive values and then a fixed tree over the block, into
+// blk[b]; finish_partials_kernel adds the block sums in index order.
+constexpr int kReduceChunk = 4096;
+
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ part, int n,
+                                                              double* __restrict__ blk) {
+    __shared__ double s[256];
+    const int base = blockIdx.x * kReduceChunk + threadIdx.x * 16;
     double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += 64) v += part[k];
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
-    if (threadIdx.x == 0) acc[0] += v;
+    for (int k = 0; k < 16; ++k)
+        if (base + k < n) v += part[base + k];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if (static_cast<int>(threadIdx.x) < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(64) finish_partials_kernel(const double* __restrict__ blk, int nb,
+                                                             double* __restrict__ acc) {
+    if (threadIdx.x != 0) return;
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += blk[b];
+    acc[0] += v;
 }
 
 // Add g (nth complex) into column i_ext of Phi (residual injection).
@@ -316,8 +337,14 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const double* part, int n, double* acc, hipStream_t stream) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, stream, part, n, acc);
+int reduce_partials_blocks(int n) { return (n + kReduceChunk - 1) / kReduceChunk; }
+
+// blk holds reduce_partials_blocks(n) doubles.
+hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int nb = reduce_partials_blocks(n);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(nb), dim3(256), 0, stream, part, n, blk);
+    hipLaunchKernelGGL(finish_partials_kernel, dim3(1), dim3(64), 0, stream, blk, nb, acc);
     return hipGetLastError();
 }
 

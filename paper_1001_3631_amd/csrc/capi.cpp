@@ -96,7 +96,8 @@ void free_adjoint(teuk_ctx* c) {
         }
     (void)hipFree(c->d_dA);
     (void)hipFree(c->d_dA_part);
-    c->d_dA = c->d_dA_part = nullptr;
+    (void)hipFree(c->d_dA_blk);
+    c->d_dA = c->d_dA_part = c->d_dA_blk = nullptr;
     c->adj_clock = -1;
 }
 
@@ -190,7 +191,8 @@ void set_tuning_fields(teuk_ctx* c, int seg, int k) {
 
 int flush_partials(teuk_ctx* c) {
     if (c->part_filled == 0) return TEUK_OK;
-    HIP_TRY(teuk::launch_reduce_partials(c->d_dA_part, c->part_items * c->part_filled, c->d_dA, c->stream),
+    HIP_TRY(teuk::launch_reduce_partials(c->d_dA_part, c->part_items * c->part_filled, c->d_dA_blk, c->d_dA,
+                                         c->stream),
             "dA reduction");
     c->part_filled = 0;
     return TEUK_OK;
@@ -479,6 +481,8 @@ int teuk_adjoint_begin(teuk_ctx* c, const void* lam_phi, const void* lam_pi, int
                 if (e == hipSuccess) e = hipMalloc(&p, plane_bytes);
         if (e == hipSuccess) e = hipMalloc(&c->d_dA, sizeof(double));
         if (e == hipSuccess) e = hipMalloc(&c->d_dA_part, sizeof(double) * max_items * kPartSteps);
+        if (e == hipSuccess)
+            e = hipMalloc(&c->d_dA_blk, sizeof(double) * teuk::reduce_partials_blocks(max_items * kPartSteps));
         if (e != hipSuccess) {
             free_adjoint(c);
             return fail(TEUK_ENOMEM, std::string("adjoint buffers: ") + hipGetErrorString(e));
@@ -632,7 +636,9 @@ int teuk_forward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, void* wav
     const bool sl = plan->state_weight != 0.0;
     if (sl && c->d_ls == nullptr) {
         hipError_t e = hipMalloc(&c->d_ls, sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&c->d_ls_part, sizeof(double) * G.nth);
+        // nth row partials, then the block sums of their reduction
+        if (e == hipSuccess)
+            e = hipMalloc(&c->d_ls_part, sizeof(double) * (G.nth + teuk::reduce_partials_blocks(G.nth)));
         if (e != hipSuccess) return fail(TEUK_ENOMEM, "state-loss buffers");
     }
     if (sl) HIP_TRY(hipMemsetAsync(c->d_ls, 0, sizeof(double), c->stream), "state loss zero");
@@ -653,7 +659,8 @@ int teuk_forward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, void* wav
             if (n + 1 >= plan->n_lo && n + 1 <= plan->n_hi) {
                 HIP_TRY(teuk::launch_region_sumsq(c->plane[c->cur][0], c->ld, plan->i0, plan->i1, plan->j0,
                                                   plan->j1, c->d_ls_part, c->stream), "state loss");
-                HIP_TRY(teuk::launch_reduce_partials(c->d_ls_part, plan->j1 - plan->j0, c->d_ls, c->stream),
+                HIP_TRY(teuk::launch_reduce_partials(c->d_ls_part, plan->j1 - plan->j0, c->d_ls_part + G.nth,
+                                                     c->d_ls, c->stream),
                         "state loss reduction");
             }
         }

@@ -63,6 +63,7 @@ struct teuk_ctx {
     int64_t adj_clock = -1;
     double* d_dA = nullptr;        // accumulated dL/dA (device)
     double* d_dA_part = nullptr;   // per-wave partials of a run of adjoint iterations
+    double* d_dA_blk = nullptr;    // block sums of the partials (fixed-order reduction)
     int part_items = 0;            // partials per iteration (waves of the adjoint launch)
     int part_filled = 0;           // iterations written since the last reduction
     // checkpointed gradient

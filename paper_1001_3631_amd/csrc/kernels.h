@@ -118,7 +118,8 @@ hipError_t launch_add_region(double2* lam, int ld, const double2* src, int src_l
 
 bool valid_segment_rows(int seg);
 hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream);
-hipError_t launch_reduce_partials(const double* part, int n, double* acc, hipStream_t stream);
+int reduce_partials_blocks(int n);
+hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream);
 hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream);
 hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const double2* gb, int nr, int nth,
                              int ld, hipStream_t stream);
