@@ -77,14 +77,17 @@ __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
 }  // namespace
 
 template <int SEG>
-__global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
+__global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
     // rows jlo-4 .. jhi+5 (jhi - jlo <= SEG + 2).  Output row r needs mu rows
     // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
     constexpr int NT = SEG + 12;
     const int lane = threadIdx.x & 63;
     const int wg = a_xcd_remap(blockIdx.x, gridDim.x);
-    const int item = wg * 4 + (threadIdx.x >> 6);
-    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
+    // wave-uniform work item in a scalar register (row branches become scalar
+    // and the angular records, a separate __restrict__ argument, are fetched
+    // through the scalar cache)
+    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+    if (item >= P.nstrips * P.nseg) return;
     const int strip = item / P.nseg;
     const int seg = item - strip * P.nseg;
     const int i = strip * 62 - 1 + lane;
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
             mQ[k] = q;
             nQ[k] = nD[k] = nDQ[k] = nC[k] = nW[k] = cz();
             if (interior_row && interior_col) {
-                const ThetaRow R = P.rows[r];
+                const ThetaRow R = rows[r];
                 const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi' = Phi + dt (Pi~ - b dPhi);  Pi' = Pi + dt (b dPi + S),
                 // S = -c_t Pi~ + m_r dPhi + C_0 Phi~ + w Ang[Phi~] + F
@@ -170,9 +173,9 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
             double2 ptil = cz();
             if (r1 >= 0 && r1 < nth) {
                 ptil = nC[k];
-                if (r1 - 1 >= 1) ptil = axpy(ang_weights(P.rows[r1 - 1]).alpha, nW[k - 1], ptil);
-                if (r1 >= 1 && r1 <= nth - 2) ptil = axpy(ang_weights(P.rows[r1]).beta, nW[k], ptil);
-                if (r1 + 1 <= nth - 2) ptil = axpy(ang_weights(P.rows[r1 + 1]).gamma, nW[k + 1], ptil);
+                if (r1 - 1 >= 1) ptil = axpy(ang_weights(rows[r1 - 1]).alpha, nW[k - 1], ptil);
+                if (r1 >= 1 && r1 <= nth - 2) ptil = axpy(ang_weights(rows[r1]).beta, nW[k], ptil);
+                if (r1 + 1 <= nth - 2) ptil = axpy(ang_weights(rows[r1 + 1]).gamma, nW[k + 1], ptil);
             }
             // contributions of node i to its right half (i+1/2) and left half (i-1/2)
             const double2 a = make_double2(0.5 * ptil.x, 0.5 * ptil.y);
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
                     if (r2 == nth - 2) { p = axpy(four_thirds, hP[k + 1], p); q = axpy(four_thirds, hQ[k + 1], q); }
                     if (r2 == nth - 3) { p = axpy(-third, hP[k + 2], p); q = axpy(-third, hQ[k + 2], q); }
                 }
-                const ThetaRow R = P.rows[r2];
+                const ThetaRow R = rows[r2];
                 const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi^h = Phi~ + hdt (Pi~ - b dPhi);  Pi^h = Pi~ + hdt (b dPi + S)
                 yW[k] = make_double2(hdt * c.w * q.x, hdt * c.w * q.y);
@@ -226,9 +229,9 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P) {
             double2 pb = cz();
             if (r3 >= 0 && r3 < nth) {
                 pb = cC[k];
-                if (r3 - 1 >= 1) pb = axpy(ang_weights(P.rows[r3 - 1]).alpha, yW[k - 1], pb);
-                if (r3 >= 1 && r3 <= nth - 2) pb = axpy(ang_weights(P.rows[r3]).beta, yW[k], pb);
-                if (r3 + 1 <= nth - 2) pb = axpy(ang_weights(P.rows[r3 + 1]).gamma, yW[k + 1], pb);
+                if (r3 - 1 >= 1) pb = axpy(ang_weights(rows[r3 - 1]).alpha, yW[k - 1], pb);
+                if (r3 >= 1 && r3 <= nth - 2) pb = axpy(ang_weights(rows[r3]).beta, yW[k], pb);
+                if (r3 + 1 <= nth - 2) pb = axpy(ang_weights(rows[r3 + 1]).gamma, yW[k + 1], pb);
             }
             // half i+1/2 gives its left node (i) 1/2 avg - diff/h, its right node (i+1) 1/2 avg + diff/h
             const double2 hpP = make_double2(0.5 * pb.x, 0.5 * pb.y);
@@ -329,9 +332,9 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream) {
     const int items = P.nstrips * P.nseg;
     const dim3 grid((items + 3) / 4), block(256);
     switch (seg) {
-        case 4: hipLaunchKernelGGL(lw_adjoint_kernel<4>, grid, block, 0, stream, P); break;
-        case 8: hipLaunchKernelGGL(lw_adjoint_kernel<8>, grid, block, 0, stream, P); break;
-        case 16: hipLaunchKernelGGL(lw_adjoint_kernel<16>, grid, block, 0, stream, P); break;
+        case 4: hipLaunchKernelGGL(lw_adjoint_kernel<4>, grid, block, 0, stream, P, P.rows); break;
+        case 8: hipLaunchKernelGGL(lw_adjoint_kernel<8>, grid, block, 0, stream, P, P.rows); break;
+        case 16: hipLaunchKernelGGL(lw_adjoint_kernel<16>, grid, block, 0, stream, P, P.rows); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

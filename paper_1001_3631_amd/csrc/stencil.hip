@@ -83,11 +83,12 @@ struct LevelArgs {
     int lbase;
 };
 
-template <int NROW, bool IN_LDS, bool OUT_LDS>
 // Parameters are taken by value: with references the compiler must assume
 // that the output stores may alias them and re-reads fields after each store.
+// rows is the kernel's __restrict__ argument where it has one (scalar loads).
+template <int NROW, bool IN_LDS, bool OUT_LDS>
 __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs A, const RCol rn,
-                                             const RCol rh) {
+                                             const RCol rh, const ThetaRow* __restrict__ rows) {
     const int nth = P.nth;
     const int ld = P.ld;
     const int i = A.i;
@@ -146,7 +147,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                 hP[t - 1] = z;
                 hQ[t - 1] = z;
                 if (jh >= 1 && jh <= nth - 2) {
-                    const ThetaRow R = P.rows[jh];
+                    const ThetaRow R = rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                     const double2 F = src_lookup(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh);
                     lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
@@ -173,7 +174,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                     double2 oP = z, oQ = z;
                     const bool pole = (jf == 0) || (jf == nth - 1);
                     if (!pole && interior_col) {
-                        const ThetaRow R = P.rows[jf];
+                        const ThetaRow R = rows[jf];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                         const double2 F = src_lookup(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf);
                         // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
@@ -228,10 +229,14 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
 // faster than the same code reached through the inlined template (same
 // instructions on every point, so the results are bitwise identical).
 template <int SEG>
-__global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
+__global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaRow* __restrict__ rows) {
     const int lane = threadIdx.x & 63;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int item = wg * 4 + (threadIdx.x >> 6);
+    // the wave's work item, in a scalar register: everything derived from it
+    // (segment rows, row branches, angular-record addresses) is then known to
+    // be wave-uniform, so the row branches are scalar and the records are
+    // fetched through the scalar cache
+    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
     if (item >= P.nstrips * P.nseg) return;   // uniform per wave
     const int strip = item / P.nseg;
     const int seg = item - strip * P.nseg;
@@ -283,7 +288,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                 hP[t - 1] = z;
                 hQ[t - 1] = z;
                 if (jh >= 1 && jh <= nth - 2) {
-                    const ThetaRow R = P.rows[jh];
+                    const ThetaRow R = rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                     const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
                     lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
@@ -310,7 +315,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
                     double2 oP = z, oQ = z;
                     const bool pole = (jf == 0) || (jf == nth - 1);
                     if (!pole && interior_col) {
-                        const ThetaRow R = P.rows[jf];
+                        const ThetaRow R = rows[jf];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                         const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
                         // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
@@ -377,7 +382,8 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P) {
 // block is bitwise identical to K single iterations.
 template <int SEG, int K, int L>
 __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, int jlo, int jhi,
-                                             const RCol& rn, const RCol& rh) {
+                                             const RCol& rn, const RCol& rh,
+                                             const ThetaRow* __restrict__ rows) {
     constexpr int NROW = SEG + 2 + 4 * (K - L);
     A.lo = max(0, jlo - 2 * (K - L));
     A.hi = min(P.nth, jhi + 2 * (K - L));
@@ -387,12 +393,12 @@ __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, 
     A.org = make_int4(0, 0, 0, 0);
     if (P.org != nullptr) A.org = P.org[L - 1];
     A.wave = P.wave ? P.wave + static_cast<size_t>(L - 1) * P.nth : nullptr;
-    stream_level<NROW, (L > 1), (L < K)>(P, A, rn, rh);
-    if constexpr (L < K) block_levels<SEG, K, L + 1>(P, A, jlo, jhi, rn, rh);
+    stream_level<NROW, (L > 1), (L < K)>(P, A, rn, rh, rows);
+    if constexpr (L < K) block_levels<SEG, K, L + 1>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 template <int SEG, int K>
-__global__ void __launch_bounds__(64) lw_block_kernel(StepParams P) {
+__global__ void __launch_bounds__(64) lw_block_kernel(StepParams P, const ThetaRow* __restrict__ rows) {
     constexpr int ROWS = SEG + 2 + 4 * (K - 1);
     __shared__ double2 bufP[ROWS * 64];
     __shared__ double2 bufQ[ROWS * 64];
@@ -413,7 +419,7 @@ __global__ void __launch_bounds__(64) lw_block_kernel(StepParams P) {
     const int ih = min(max(A.i, 0), P.nr - 2);
     const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
     const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
-    block_levels<SEG, K, 1>(P, A, jlo, jhi, rn, rh);
+    block_levels<SEG, K, 1>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 // Batched persistent stepping: many independent instances (each its own
@@ -524,7 +530,7 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         for (int q = 0; q < P.nseg; ++q) {
             A.lo = q * SEG;
             A.hi = (q == P.nseg - 1) ? P.nth : A.lo + SEG;
-            stream_level<SEG + 2, false, false>(P, A, rn, rh);
+            stream_level<SEG + 2, false, false>(P, A, rn, rh, P.rows);
         }
 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -650,9 +656,11 @@ hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEven
     const int items = P.nstrips * P.nseg;
     const dim3 grid((items + 3) / 4), block(256);
     switch (seg) {
-        case 4: hipExtLaunchKernelGGL(lw_step_kernel<4>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
-        case 8: hipExtLaunchKernelGGL(lw_step_kernel<8>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
-        case 16: hipExtLaunchKernelGGL(lw_step_kernel<16>, grid, block, 0, stream, ev_start, ev_stop, 0, P); break;
+        // the angular records are a separate __restrict__ argument: read-only,
+        // never aliasing the planes, so their wave-uniform loads are scalar
+        case 4: hipExtLaunchKernelGGL(lw_step_kernel<4>, grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows); break;
+        case 8: hipExtLaunchKernelGGL(lw_step_kernel<8>, grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows); break;
+        case 16: hipExtLaunchKernelGGL(lw_step_kernel<16>, grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -673,11 +681,11 @@ hipError_t launch_block(const StepParams& P, int seg, int k, hipStream_t stream,
                         hipEvent_t ev_stop) {
     const dim3 grid(P.nstrips * P.nseg), block(64);
     if (seg == 4 && k == 2)
-        hipExtLaunchKernelGGL((lw_block_kernel<4, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+        hipExtLaunchKernelGGL((lw_block_kernel<4, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows);
     else if (seg == 8 && k == 2)
-        hipExtLaunchKernelGGL((lw_block_kernel<8, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+        hipExtLaunchKernelGGL((lw_block_kernel<8, 2>), grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows);
     else if (seg == 4 && k == 4)
-        hipExtLaunchKernelGGL((lw_block_kernel<4, 4>), grid, block, 0, stream, ev_start, ev_stop, 0, P);
+        hipExtLaunchKernelGGL((lw_block_kernel<4, 4>), grid, block, 0, stream, ev_start, ev_stop, 0, P, P.rows);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
