@@ -14,6 +14,12 @@
 
 namespace teuk {
 
+// Rows of u^n the single-step kernel fetches ahead of their use.
+#ifndef TEUK_PREFETCH_ROWS
+#define TEUK_PREFETCH_ROWS 2
+#endif
+constexpr int kPrefetchRows = TEUK_PREFETCH_ROWS;
+
 namespace {
 
 // Cross-lane moves with DPP wave shifts (no LDS traffic): from_next gives lane
@@ -264,15 +270,31 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
     double2 oP1 = z, oQ1 = z;             // full-step row 1 (for the pole row 0)
     double2 oPp = z, oQp = z;             // previous full-step row (for the last pole row)
 
+    // Software prefetch: row t of u^n is fetched PF iterations before it is
+    // used, at a clamped (always valid) address and unconditionally, so its
+    // latency overlaps the arithmetic of the rows in between; out-of-range
+    // rows and columns are masked to zero where they are used.
+    constexpr int PF = kPrefetchRows;
+    double2 fP[SEG + 6], fQ[SEG + 6];
+    const int icl = min(max(i, 0), P.nr - 1);
+    auto fetch = [&](int t) {
+        const int jc = min(max(jlo - 2 + t, 0), nth - 1);
+        fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
+        fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
+    };
+#pragma unroll
+    for (int t = 0; t < PF && t < SEG + 6; ++t) fetch(t);
+
 #pragma unroll
     for (int t = 0; t < SEG + 6; ++t) {
+        if (t + PF < SEG + 6) fetch(t + PF);
         const int jj = jlo - 2 + t;
         if (jj <= jhi + 1) {
-            // ---- load row jj of u^n and form column sums/differences ----
+            // ---- row jj of u^n and its column sums/differences ----
             double2 p = z, q = z;
             if (jj >= 0 && jj < nth && in_col) {
-                p = P.phi[static_cast<size_t>(jj) * ld + i];
-                q = P.pi[static_cast<size_t>(jj) * ld + i];
+                p = fP[t];
+                q = fQ[t];
             }
             uP[t] = p;
             uQ[t] = q;
