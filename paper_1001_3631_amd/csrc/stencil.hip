@@ -19,6 +19,12 @@ namespace teuk {
 #define TEUK_PREFETCH_ROWS 2
 #endif
 constexpr int kPrefetchRows = TEUK_PREFETCH_ROWS;
+// The batched kernel holds more state per wave (instance fields); with the
+// prefetch its register count would leave one wave per SIMD.
+#ifndef TEUK_BATCH_PREFETCH_ROWS
+#define TEUK_BATCH_PREFETCH_ROWS 0
+#endif
+constexpr int kBatchPrefetchRows = TEUK_BATCH_PREFETCH_ROWS;
 
 namespace {
 
@@ -92,7 +98,7 @@ struct LevelArgs {
 // Parameters are taken by value: with references the compiler must assume
 // that the output stores may alias them and re-reads fields after each store.
 // rows is the kernel's __restrict__ argument where it has one (scalar loads).
-template <int NROW, bool IN_LDS, bool OUT_LDS>
+template <int NROW, bool IN_LDS, bool OUT_LDS, int PREFETCH = kPrefetchRows>
 __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs A, const RCol rn,
                                              const RCol rh, const ThetaRow* __restrict__ rows) {
     const int nth = P.nth;
@@ -124,11 +130,25 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
         }
     };
 
+    // Rows read from the planes are fetched PREFETCH iterations ahead at
+    // clamped addresses (as in lw_step_kernel); LDS rows are read in place.
+    constexpr int PF = IN_LDS ? 0 : PREFETCH;
+    double2 fP[NROW + 4], fQ[NROW + 4];
+    const int icl = min(max(i, 0), P.nr - 1);
+    auto fetch = [&](int t) {
+        const int jc = min(max(lo - 2 + t, 0), nth - 1);
+        fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
+        fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
+    };
+#pragma unroll
+    for (int t = 0; t < PF && t < NROW + 4; ++t) fetch(t);
+
 #pragma unroll
     for (int t = 0; t < NROW + 4; ++t) {
+        if (!IN_LDS && t + PF < NROW + 4) fetch(t + PF);
         const int jj = lo - 2 + t;
         if (jj <= hi + 1) {
-            // ---- load row jj of the input level and form column sums/differences ----
+            // ---- row jj of the input level and its column sums/differences ----
             double2 p = z, q = z;
             if (IN_LDS) {
                 if (jj >= 0 && jj < nth) {
@@ -136,8 +156,8 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                     q = A.lq[(jj - A.lbase) * 64 + lane];
                 }
             } else if (jj >= 0 && jj < nth && in_col) {
-                p = P.phi[static_cast<size_t>(jj) * ld + i];
-                q = P.pi[static_cast<size_t>(jj) * ld + i];
+                p = fP[t];
+                q = fQ[t];
             }
             uP[t] = p;
             uQ[t] = q;
@@ -552,7 +572,7 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         for (int q = 0; q < P.nseg; ++q) {
             A.lo = q * SEG;
             A.hi = (q == P.nseg - 1) ? P.nth : A.lo + SEG;
-            stream_level<SEG + 2, false, false>(P, A, rn, rh, P.rows);
+            stream_level<SEG + 2, false, false, kBatchPrefetchRows>(P, A, rn, rh, P.rows);
         }
 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
