@@ -1,0 +1,153 @@
+// Batched persistent stepping of many independent instances.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "lw_point.h"
+#include "stream_level.h"
+
+namespace teuk {
+
+// Batched persistent stepping: many independent instances (each its own
+// grid, coefficients and planes) advance `rounds` iterations in one launch.
+// Work item = one tile of one iteration, a tile being a strip of 62 columns
+// of one instance over all its theta rows (the wave streams the segments of
+// SEG rows one after another, reusing its radial records).  Each workgroup
+// is one wave; each pass of its loop takes the next item from a global
+// counter, in iteration-major order: every tile of iteration n before any
+// tile of n + 1.  The counter value and the abort flag reach all lanes
+// through LDS between two barriers, so every lane holds the same item without
+// relying on lanes reconverging on their own.
+//
+// Dependencies: the item (tile, n) reads u^n on its strip plus one column on
+// each side, inside the strips s - 1, s, s + 1, and writes the level that
+// those strips read at iteration n - 1.  It therefore waits until each of
+// them has completed n iterations (done >= n), then publishes done = n + 1.
+// Every wait is on an item with a smaller ticket; a ticket is only handed
+// out at the top of a pass and is processed right away, so its holder is
+// running and the smallest unfinished ticket never waits: every wait ends.
+// A wait longer than wait_limit (a broken invariant) sets *abort, and every
+// wave leaves at the top of its next pass.  Tile data is made visible across
+// the XCDs' L2 caches by an agent-scope release after the tile's stores and
+// an agent-scope acquire after the wait.
+template <int SEG>
+__global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
+    __shared__ unsigned long long s_t;
+    __shared__ int s_stop;
+    const int lane = threadIdx.x;
+    const unsigned long long total = static_cast<unsigned long long>(B.rounds) * B.ntiles;
+    while (true) {
+        __syncthreads();                     // the previous pass has read s_t / s_stop
+        if (lane == 0) {
+            s_t = __hip_atomic_fetch_add(B.ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_stop = __hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const unsigned long long tv = s_t;
+        if (s_stop != 0 || tv >= total) break;            // the same decision in every lane
+        // equal in every lane: move it to scalar registers
+        const unsigned long long t =
+            (static_cast<unsigned long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv >> 32))) << 32) |
+            static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv & 0xffffffffu)));
+
+        const int n = static_cast<int>(t / static_cast<unsigned long long>(B.ntiles));
+        const int k = static_cast<int>(t - static_cast<unsigned long long>(n) * B.ntiles);
+        const int4 tile = B.tiles[k];
+        const BatchInstance& I = B.inst[tile.x];
+        const int strip = tile.y;
+
+        if (n > 0 && lane < 3) {
+            const int s2 = strip + lane - 1;
+            if (s2 >= 0 && s2 < I.nstrips) {
+                const int* f = B.done + I.tile0 + s2;
+                const long long t0 = wall_clock64();
+                while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
+                    if (__hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                    if (wall_clock64() - t0 > B.wait_limit) {
+                        __hip_atomic_store(B.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        // after an abort the item is still computed (on whatever data is
+        // there); the host reports the abort and the states are invalid
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        StepParams P;
+        const int lv = (I.cur + n) & 1;
+        P.phi = I.plane[lv][0];
+        P.pi = I.plane[lv][1];
+        P.phi_out = I.plane[lv ^ 1][0];
+        P.pi_out = I.plane[lv ^ 1][1];
+        P.rnode = I.rnode;
+        P.rhalf = I.rhalf;
+        P.rows = I.rows;
+        P.nr = I.nr;
+        P.nth = I.nth;
+        P.ld = I.ld;
+        P.rpitch = I.rpitch;
+        P.nstrips = I.nstrips;
+        P.nseg = I.nseg;
+        P.dt = I.dt;
+        P.inv_hr = I.inv_hr;
+        P.ko_c = I.ko_c;
+        P.even = I.even;
+        P.kerr = I.kerr;
+        P.i_ext = I.i_ext;
+        P.wave = nullptr;
+        P.fh = P.fn = nullptr;
+        P.org = nullptr;
+        P.win_r = P.win_t = 0;
+        LevelArgs A;
+        A.lane = lane;
+        A.i = strip * 62 - 1 + lane;
+        A.halo = 1;
+        A.fh = A.fn = nullptr;
+        A.org = make_int4(0, 0, 0, 0);
+        A.wave = I.wave ? I.wave + static_cast<size_t>(n) * P.nth : nullptr;
+        A.lp = A.lq = nullptr;
+        A.lbase = 0;
+        const int ic = min(max(A.i, 0), P.nr - 1);
+        const int ih = min(max(A.i, 0), P.nr - 2);
+        const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+        const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+        for (int q = 0; q < P.nseg; ++q) {
+            A.lo = q * SEG;
+            A.hi = (q == P.nseg - 1) ? P.nth : A.lo + SEG;
+            stream_level<SEG + 2, false, false, kBatchPrefetchRows>(P, A, rn, rh, P.rows);
+        }
+
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(B.done + tile.w, n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Zero the work counter and the per-tile counters (a kernel, so that it can
+// be a node of a captured graph).  The abort flag is left alone: once set, it
+// stays set (and later launches exit at once) until the host has read it.
+__global__ void __launch_bounds__(256) batch_reset_kernel(BatchParams B) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *B.ticket = 0ull;
+    if (e < B.ntiles) B.done[e] = 0;
+}
+
+hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((B.ntiles + 255) / 256), dim3(256), 0, stream, B);
+    return hipGetLastError();
+}
+
+// waves = persistent waves to start (one per workgroup); every wave loops
+// over the work counter, so any positive number is correct.
+hipError_t launch_batch(const BatchParams& B, int seg, int waves, hipStream_t stream) {
+    const dim3 grid(waves), block(64);
+    switch (seg) {
+        case 4: hipLaunchKernelGGL(lw_batch_kernel<4>, grid, block, 0, stream, B); break;
+        case 8: hipLaunchKernelGGL(lw_batch_kernel<8>, grid, block, 0, stream, B); break;
+        case 16: hipLaunchKernelGGL(lw_batch_kernel<16>, grid, block, 0, stream, B); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace teuk
