@@ -7,6 +7,32 @@
 
 namespace teuk {
 
+// Rows of u^n fetched ahead in the batched kernel.  It keeps its instance
+// fields in scalar registers, which leaves room for the same prefetch as the
+// single-step kernel at two waves per SIMD.
+#ifndef TEUK_BATCH_PREFETCH_ROWS
+#define TEUK_BATCH_PREFETCH_ROWS 2
+#endif
+constexpr int kBatchPrefetchRows = TEUK_BATCH_PREFETCH_ROWS;
+
+namespace {
+
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned long long hi = static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(a >> 32)));
+    const unsigned long long lo = static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(a)));
+    return reinterpret_cast<T*>((hi << 32) | lo);
+}
+
+}  // namespace
+
 // Batched persistent stepping: many independent instances (each its own
 // grid, coefficients and planes) advance `rounds` iterations in one launch.
 // Work item = one tile of one iteration, a tile being a strip of 62 columns
@@ -42,12 +68,14 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
             s_stop = __hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
+        // every lane read the same values: move them to scalar registers, so
+        // that the exit and everything after it are wave-uniform
         const unsigned long long tv = s_t;
-        if (s_stop != 0 || tv >= total) break;            // the same decision in every lane
-        // equal in every lane: move it to scalar registers
         const unsigned long long t =
             (static_cast<unsigned long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv >> 32))) << 32) |
             static_cast<unsigned int>(__builtin_amdgcn_readfirstlane(static_cast<int>(tv & 0xffffffffu)));
+        const int stop = __builtin_amdgcn_readfirstlane(s_stop);
+        if (stop != 0 || t >= total) break;
 
         const int n = static_cast<int>(t / static_cast<unsigned long long>(B.ntiles));
         const int k = static_cast<int>(t - static_cast<unsigned long long>(n) * B.ntiles);
@@ -74,38 +102,41 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         // there); the host reports the abort and the states are invalid
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
+        // the instance's fields are the same in every lane: keep them in
+        // scalar registers (the vector registers go to the stencil)
         StepParams P;
-        const int lv = (I.cur + n) & 1;
-        P.phi = I.plane[lv][0];
-        P.pi = I.plane[lv][1];
-        P.phi_out = I.plane[lv ^ 1][0];
-        P.pi_out = I.plane[lv ^ 1][1];
-        P.rnode = I.rnode;
-        P.rhalf = I.rhalf;
-        P.rows = I.rows;
-        P.nr = I.nr;
-        P.nth = I.nth;
-        P.ld = I.ld;
-        P.rpitch = I.rpitch;
-        P.nstrips = I.nstrips;
-        P.nseg = I.nseg;
-        P.dt = I.dt;
-        P.inv_hr = I.inv_hr;
-        P.ko_c = I.ko_c;
-        P.even = I.even;
-        P.kerr = I.kerr;
-        P.i_ext = I.i_ext;
+        const int lv = uni(I.cur + n) & 1;
+        P.phi = uni(I.plane[lv][0]);
+        P.pi = uni(I.plane[lv][1]);
+        P.phi_out = uni(I.plane[lv ^ 1][0]);
+        P.pi_out = uni(I.plane[lv ^ 1][1]);
+        P.rnode = uni(I.rnode);
+        P.rhalf = uni(I.rhalf);
+        P.rows = uni(I.rows);
+        P.nr = uni(I.nr);
+        P.nth = uni(I.nth);
+        P.ld = uni(I.ld);
+        P.rpitch = uni(I.rpitch);
+        P.nstrips = uni(I.nstrips);
+        P.nseg = uni(I.nseg);
+        P.dt = uni(I.dt);
+        P.inv_hr = uni(I.inv_hr);
+        P.ko_c = uni(I.ko_c);
+        P.even = uni(I.even);
+        P.kerr = uni(I.kerr);
+        P.i_ext = uni(I.i_ext);
         P.wave = nullptr;
         P.fh = P.fn = nullptr;
         P.org = nullptr;
         P.win_r = P.win_t = 0;
+        double2* const wave = uni(I.wave);
         LevelArgs A;
         A.lane = lane;
         A.i = strip * 62 - 1 + lane;
         A.halo = 1;
         A.fh = A.fn = nullptr;
         A.org = make_int4(0, 0, 0, 0);
-        A.wave = I.wave ? I.wave + static_cast<size_t>(n) * P.nth : nullptr;
+        A.wave = wave ? wave + static_cast<size_t>(n) * P.nth : nullptr;
         A.lp = A.lq = nullptr;
         A.lbase = 0;
         const int ic = min(max(A.i, 0), P.nr - 1);

@@ -16,12 +16,6 @@ namespace teuk {
 #define TEUK_PREFETCH_ROWS 2
 #endif
 constexpr int kPrefetchRows = TEUK_PREFETCH_ROWS;
-// The batched kernel holds more state per wave (instance fields); with the
-// prefetch its register count would leave one wave per SIMD.
-#ifndef TEUK_BATCH_PREFETCH_ROWS
-#define TEUK_BATCH_PREFETCH_ROWS 0
-#endif
-constexpr int kBatchPrefetchRows = TEUK_BATCH_PREFETCH_ROWS;
 
 namespace {
 
