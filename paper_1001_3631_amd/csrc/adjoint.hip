@@ -24,17 +24,12 @@
 
 #include "kernels.h"
 #include "lw_point.h"
+#include "stream_level.h"   // wave shifts (from_next, from_prev)
 
 namespace teuk {
 
 namespace {
 
-__device__ __forceinline__ double2 a_shfl_dn1(double2 v) {
-    return make_double2(__shfl_down(v.x, 1), __shfl_down(v.y, 1));
-}
-__device__ __forceinline__ double2 a_shfl_up1(double2 v) {
-    return make_double2(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
-}
 __device__ __forceinline__ double2 cz() { return make_double2(0.0, 0.0); }
 // conj(c) * z
 __device__ __forceinline__ double2 cmul_conj(double2 c, double2 z) {
@@ -183,7 +178,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const double2 aq = make_double2(0.5 * nQ[k].x, 0.5 * nQ[k].y);
             const double2 dqv = make_double2(nDQ[k].x * inv_hr, nDQ[k].y * inv_hr);
             const double2 leftP = c_sub(a, d), leftQ = c_sub(aq, dqv);
-            const double2 nbP = a_shfl_dn1(leftP), nbQ = a_shfl_dn1(leftQ);   // node i+1's left part
+            const double2 nbP = from_next(leftP), nbQ = from_next(leftQ);   // node i+1's left part
             if (has_half) {
                 hP[k] = c_add(c_add(a, d), nbP);
                 hQ[k] = c_add(c_add(aq, dqv), nbQ);
@@ -239,7 +234,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const double2 hpQ = make_double2(0.5 * qb[k].x, 0.5 * qb[k].y);
             const double2 hdQ = make_double2(dq[k].x * inv_hr, dq[k].y * inv_hr);
             const double2 rightP = c_add(hpP, hdP), rightQ = c_add(hpQ, hdQ);
-            const double2 fromLeftP = a_shfl_up1(rightP), fromLeftQ = a_shfl_up1(rightQ);
+            const double2 fromLeftP = from_prev(rightP), fromLeftQ = from_prev(rightQ);
             if (r3 >= jlo && r3 < jhi && writer) {
                 double2 oP = c_add(c_sub(hpP, hdP), (i >= 1) ? fromLeftP : cz());
                 double2 oQ = c_add(c_sub(hpQ, hdQ), (i >= 1) ? fromLeftQ : cz());
