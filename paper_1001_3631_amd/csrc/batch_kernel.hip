@@ -143,10 +143,16 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         const int ih = min(max(A.i, 0), P.nr - 2);
         const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
         const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+        // segments away from the poles on a strip of interior columns take
+        // the interior form of the level (the same arithmetic)
+        const bool cols_interior = strip >= 1 && strip * 62 + 64 <= P.nr;
         for (int q = 0; q < P.nseg; ++q) {
             A.lo = q * SEG;
             A.hi = (q == P.nseg - 1) ? P.nth : A.lo + SEG;
-            stream_level<SEG + 2, false, false, kBatchPrefetchRows>(P, A, rn, rh, P.rows);
+            if (cols_interior && q != P.nseg - 1 && A.lo >= 4 && A.hi <= P.nth - 2)
+                stream_level<SEG + 2, false, false, kBatchPrefetchRows, SEG>(P, A, rn, rh, P.rows);
+            else
+                stream_level<SEG + 2, false, false, kBatchPrefetchRows>(P, A, rn, rh, P.rows);
         }
 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -15,8 +15,9 @@ namespace teuk {
 // u^n at j-2..j+2) and one column on each side, so the 64 lanes end with
 // 64 - 2K owner columns.  Levels 1..K-1 stay in this wave's LDS buffer; only
 // level K is written to HBM.  Every point goes through stream_level, so a
-// block is bitwise identical to K single iterations.
-template <int SEG, int K, int L>
+// block is bitwise identical to K single iterations.  FAST: every level is
+// interior (see stream_level) and has SEG + 4(K - L) rows.
+template <int SEG, int K, int L, bool FAST>
 __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, int jlo, int jhi,
                                              const RCol& rn, const RCol& rh,
                                              const ThetaRow* __restrict__ rows) {
@@ -29,8 +30,8 @@ __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, 
     A.org = make_int4(0, 0, 0, 0);
     if (P.org != nullptr) A.org = P.org[L - 1];
     A.wave = P.wave ? P.wave + static_cast<size_t>(L - 1) * P.nth : nullptr;
-    stream_level<NROW, (L > 1), (L < K)>(P, A, rn, rh, rows);
-    if constexpr (L < K) block_levels<SEG, K, L + 1>(P, A, jlo, jhi, rn, rh, rows);
+    stream_level<NROW, (L > 1), (L < K), kPrefetchRows, FAST ? SEG + 4 * (K - L) : 0>(P, A, rn, rh, rows);
+    if constexpr (L < K) block_levels<SEG, K, L + 1, FAST>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 template <int SEG, int K>
@@ -55,7 +56,15 @@ __global__ void __launch_bounds__(64) lw_block_kernel(StepParams P, const ThetaR
     const int ih = min(max(A.i, 0), P.nr - 2);
     const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
     const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
-    block_levels<SEG, K, 1>(P, A, jlo, jhi, rn, rh, rows);
+    // level 1 (the widest) away from the poles and every lane an interior
+    // column: then every level is, and all take the interior form
+    const int i0 = strip * (64 - 2 * K) - K;
+    const bool interior = i0 >= 1 && i0 + 63 <= P.nr - 2 && seg != P.nseg - 1 &&
+                          jlo - 2 * (K - 1) >= 4 && jhi + 2 * (K - 1) <= P.nth - 2;
+    if (interior)   // uniform per wave
+        block_levels<SEG, K, 1, true>(P, A, jlo, jhi, rn, rh, rows);
+    else
+        block_levels<SEG, K, 1, false>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 bool valid_block(int seg, int k) {

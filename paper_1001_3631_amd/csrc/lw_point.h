@@ -71,6 +71,11 @@ __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin
 __device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 c_scale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// v where keep holds, else zero (component selects: a select of the whole
+// pair can be lowered through a private-memory array).
+__device__ __forceinline__ double2 masked(bool keep, double2 v) {
+    return make_double2(keep ? v.x : 0.0, keep ? v.y : 0.0);
+}
 
 // One point of either half of the iteration.  Inputs are column sums and
 // differences of the level being differenced (u^n for the half step, the

@@ -10,6 +10,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "lw_point.h"
 #include "stream_level.h"
@@ -54,135 +56,158 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
     const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
 
     const double2 z = make_double2(0.0, 0.0);
-    double2 uP[SEG + 6], uQ[SEG + 6];     // u^n, own column, rows jlo-2+t
-    double2 sP[SEG + 6], sQ[SEG + 6], dP[SEG + 6], dQ[SEG + 6];
-    double2 hP[SEG + 6], hQ[SEG + 6];     // half-step values at i+1/2, rows jlo-2+t
-    double2 gP[SEG + 6], gQ[SEG + 6];     // half-step values at i-1/2 (from lane-1)
-    double2 oP1 = z, oQ1 = z;             // full-step row 1 (for the pole row 0)
-    double2 oPp = z, oQp = z;             // previous full-step row (for the last pole row)
 
-    // Software prefetch: row t of u^n is fetched PF iterations before it is
-    // used, at a clamped (always valid) address and unconditionally, so its
-    // latency overlaps the arithmetic of the rows in between; out-of-range
-    // rows and columns are masked to zero where they are used.
-    constexpr int PF = kPrefetchRows;
-    double2 fP[SEG + 6], fQ[SEG + 6];
-    const int icl = min(max(i, 0), P.nr - 1);
-    auto fetch = [&](int t) {
-        const int jc = min(max(jlo - 2 + t, 0), nth - 1);
-        fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
-        fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
-    };
+    // The wave's rows and columns are either all interior (every row and
+    // half row in range, no pole or ghost row, every lane an interior
+    // column: most items) or not.  The body is instantiated for both cases;
+    // in the interior one the range, pole and column tests are constants, so
+    // the unrolled window carries no selects or copies for them.  Both run
+    // the same arithmetic on every point.
+    auto body = [&](auto interior_tag) {
+        constexpr bool FAST = decltype(interior_tag)::value;
+        // rows of u^n the segment reads: jlo-2 .. jhi+1 (t < NT)
+        constexpr int NT = FAST ? SEG + 4 : SEG + 6;
+        double2 uP[SEG + 6], uQ[SEG + 6];     // u^n, own column, rows jlo-2+t
+        double2 sP[SEG + 6], sQ[SEG + 6], dP[SEG + 6], dQ[SEG + 6];
+        double2 hP[SEG + 6], hQ[SEG + 6];     // half-step values at i+1/2, rows jlo-2+t
+        double2 gP[SEG + 6], gQ[SEG + 6];     // half-step values at i-1/2 (from lane-1)
+        double2 oP1 = z, oQ1 = z;             // full-step row 1 (for the pole row 0)
+        double2 oPp = z, oQp = z;             // previous full-step row (for the last pole row)
+
+        // Software prefetch: row t of u^n is fetched PF iterations before it
+        // is used, at a clamped (always valid) address and unconditionally, so
+        // its latency overlaps the arithmetic of the rows in between;
+        // out-of-range rows and columns are masked to zero where they are used.
+        constexpr int PF = kPrefetchRows;
+        double2 fP[SEG + 6], fQ[SEG + 6];
+        const int icl = min(max(i, 0), P.nr - 1);
+        auto fetch = [&](int t) {
+            const int jc = FAST ? jlo - 2 + t : min(max(jlo - 2 + t, 0), nth - 1);
+            fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
+            fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
+        };
 #pragma unroll
-    for (int t = 0; t < PF && t < SEG + 6; ++t) fetch(t);
+        for (int t = 0; t < PF && t < NT; ++t) fetch(t);
 
 #pragma unroll
-    for (int t = 0; t < SEG + 6; ++t) {
-        if (t + PF < SEG + 6) fetch(t + PF);
-        const int jj = jlo - 2 + t;
-        if (jj <= jhi + 1) {
-            // ---- row jj of u^n and its column sums/differences ----
-            double2 p = z, q = z;
-            if (jj >= 0 && jj < nth && in_col) {
-                p = fP[t];
-                q = fQ[t];
-            }
-            uP[t] = p;
-            uQ[t] = q;
-            const double2 pN = from_next(p), qN = from_next(q);
-            sP[t] = c_add(p, pN);
-            sQ[t] = c_add(q, qN);
-            dP[t] = c_sub(pN, p);
-            dQ[t] = c_sub(qN, q);
-
-            // ---- half step (lw1) at (i+1/2, jh), jh = jj - 1 ----
-            if (t >= 2) {
-                const int jh = jj - 1;
-                hP[t - 1] = z;
-                hQ[t - 1] = z;
-                if (jh >= 1 && jh <= nth - 2) {
-                    const ThetaRow R = rows[jh];
-                    const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
-                    const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
-                    lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
-                             dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
-                             c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
-                } else if (jh == nth - 1 && t >= 4) {
-                    hP[t - 1] = pole_value(P.even, hP[t - 2], hP[t - 3]);
-                    hQ[t - 1] = pole_value(P.even, hQ[t - 2], hQ[t - 3]);
+        for (int t = 0; t < NT; ++t) {
+            if (t + PF < NT) fetch(t + PF);
+            const int jj = jlo - 2 + t;
+            if (FAST || jj <= jhi + 1) {
+                // ---- row jj of u^n and its column sums/differences ----
+                double2 p = z, q = z;
+                if (FAST || (jj >= 0 && jj < nth && in_col)) {
+                    p = fP[t];
+                    q = fQ[t];
                 }
-                if (jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
-                    hP[t - 3] = pole_value(P.even, hP[t - 2], hP[t - 1]);
-                    hQ[t - 3] = pole_value(P.even, hQ[t - 2], hQ[t - 1]);
-                    gP[t - 3] = from_prev(hP[t - 3]);
-                    gQ[t - 3] = from_prev(hQ[t - 3]);
-                }
-                gP[t - 1] = from_prev(hP[t - 1]);
-                gQ[t - 1] = from_prev(hQ[t - 1]);
-            }
+                uP[t] = p;
+                uQ[t] = q;
+                const double2 pN = from_next(p), qN = from_next(q);
+                sP[t] = c_add(p, pN);
+                sQ[t] = c_add(q, qN);
+                dP[t] = c_sub(pN, p);
+                dQ[t] = c_sub(qN, q);
 
-            // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
-            if (t >= 4) {
-                const int jf = jj - 2;
-                if (jf >= jlo && jf < jhi) {
-                    double2 oP = z, oQ = z;
-                    const bool pole = (jf == 0) || (jf == nth - 1);
-                    if (!pole && interior_col) {
-                        const ThetaRow R = rows[jf];
-                        const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
-                        const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
-                        // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
-                        const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
-                        const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
-                        const double2 sPp = c_add(hP[t - 1], gP[t - 1]);
-                        const double2 sQ0 = c_add(hQ[t - 2], gQ[t - 2]);
-                        const double2 dP0 = c_sub(hP[t - 2], gP[t - 2]);
-                        const double2 dQ0 = c_sub(hQ[t - 2], gQ[t - 2]);
-                        lw_point(c, R, sPm, sP0, sPp, sQ0, dP0, dQ0, F,
-                                 P.dt, P.inv_hr, uP[t - 2], uQ[t - 2], oP, oQ);
-                        if (P.ko_c != 0.0) {
-                            const double sg = P.even ? 1.0 : -1.0;
-                            // rows jf-2 .. jf+2; ghost rows -1 and nth reflect row 1 / nth-2
-                            const double2 pm2 = (jf == 1) ? c_scale(sg, uP[t - 2]) : uP[t - 4];
-                            const double2 qm2 = (jf == 1) ? c_scale(sg, uQ[t - 2]) : uQ[t - 4];
-                            const double2 pp2 = (jf == nth - 2) ? c_scale(sg, uP[t - 2]) : uP[t];
-                            const double2 qp2 = (jf == nth - 2) ? c_scale(sg, uQ[t - 2]) : uQ[t];
-                            oP = ko_apply(oP, P.ko_c, pm2, uP[t - 3], uP[t - 2], uP[t - 1], pp2);
-                            oQ = ko_apply(oQ, P.ko_c, qm2, uQ[t - 3], uQ[t - 2], uQ[t - 1], qp2);
-                        }
+                // ---- half step (lw1) at (i+1/2, jh), jh = jj - 1 ----
+                if (t >= 2) {
+                    const int jh = jj - 1;
+                    hP[t - 1] = z;
+                    hQ[t - 1] = z;
+                    if (FAST || (jh >= 1 && jh <= nth - 2)) {
+                        const ThetaRow R = rows[jh];
+                        const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
+                        const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
+                        lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
+                                 dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
+                                 c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
+                    } else if (jh == nth - 1 && t >= 4) {
+                        hP[t - 1] = pole_value(P.even, hP[t - 2], hP[t - 3]);
+                        hQ[t - 1] = pole_value(P.even, hQ[t - 2], hQ[t - 3]);
                     }
-                    if (!pole) {
-                        if (writer) {
-                            P.phi_out[static_cast<size_t>(jf) * ld + i] = oP;
-                            P.pi_out[static_cast<size_t>(jf) * ld + i] = oQ;
-                            if (P.wave != nullptr && i == P.i_ext) P.wave[jf] = oP;
-                        }
-                        if (jf == 1) { oP1 = oP; oQ1 = oQ; }
-                        if (jf == 2) {   // pole row 0 from rows 1, 2
-                            const double2 p0 = pole_value(P.even, oP1, oP);
-                            const double2 q0 = pole_value(P.even, oQ1, oQ);
-                            if (writer) {
-                                P.phi_out[i] = interior_col ? p0 : z;
-                                P.pi_out[i] = interior_col ? q0 : z;
-                                if (P.wave != nullptr && i == P.i_ext) P.wave[0] = interior_col ? p0 : z;
+                    if (!FAST && jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
+                        hP[t - 3] = pole_value(P.even, hP[t - 2], hP[t - 1]);
+                        hQ[t - 3] = pole_value(P.even, hQ[t - 2], hQ[t - 1]);
+                        gP[t - 3] = from_prev(hP[t - 3]);
+                        gQ[t - 3] = from_prev(hQ[t - 3]);
+                    }
+                    gP[t - 1] = from_prev(hP[t - 1]);
+                    gQ[t - 1] = from_prev(hQ[t - 1]);
+                }
+
+                // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
+                if (t >= 4) {
+                    const int jf = jj - 2;
+                    if (FAST || (jf >= jlo && jf < jhi)) {
+                        double2 oP = z, oQ = z;
+                        const bool pole = !FAST && ((jf == 0) || (jf == nth - 1));
+                        if (FAST || (!pole && interior_col)) {
+                            const ThetaRow R = rows[jf];
+                            const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
+                            const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
+                            // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
+                            const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
+                            const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
+                            const double2 sPp = c_add(hP[t - 1], gP[t - 1]);
+                            const double2 sQ0 = c_add(hQ[t - 2], gQ[t - 2]);
+                            const double2 dP0 = c_sub(hP[t - 2], gP[t - 2]);
+                            const double2 dQ0 = c_sub(hQ[t - 2], gQ[t - 2]);
+                            lw_point(c, R, sPm, sP0, sPp, sQ0, dP0, dQ0, F,
+                                     P.dt, P.inv_hr, uP[t - 2], uQ[t - 2], oP, oQ);
+                            if (P.ko_c != 0.0) {
+                                const double sg = P.even ? 1.0 : -1.0;
+                                // rows jf-2 .. jf+2; ghost rows -1 and nth reflect row 1 / nth-2
+                                const bool lo_ghost = !FAST && jf == 1;
+                                const bool hi_ghost = !FAST && jf == nth - 2;
+                                const double2 pm2 = lo_ghost ? c_scale(sg, uP[t - 2]) : uP[t - 4];
+                                const double2 qm2 = lo_ghost ? c_scale(sg, uQ[t - 2]) : uQ[t - 4];
+                                const double2 pp2 = hi_ghost ? c_scale(sg, uP[t - 2]) : uP[t];
+                                const double2 qp2 = hi_ghost ? c_scale(sg, uQ[t - 2]) : uQ[t];
+                                oP = ko_apply(oP, P.ko_c, pm2, uP[t - 3], uP[t - 2], uP[t - 1], pp2);
+                                oQ = ko_apply(oQ, P.ko_c, qm2, uQ[t - 3], uQ[t - 2], uQ[t - 1], qp2);
                             }
                         }
-                        if (jf == nth - 2) {   // last pole row from rows nth-2, nth-3
-                            const double2 pl = pole_value(P.even, oP, oPp);
-                            const double2 ql = pole_value(P.even, oQ, oQp);
+                        if (!pole) {
                             if (writer) {
-                                P.phi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? pl : z;
-                                P.pi_out[static_cast<size_t>(nth - 1) * ld + i] = interior_col ? ql : z;
-                                if (P.wave != nullptr && i == P.i_ext) P.wave[nth - 1] = interior_col ? pl : z;
+                                P.phi_out[static_cast<size_t>(jf) * ld + i] = oP;
+                                P.pi_out[static_cast<size_t>(jf) * ld + i] = oQ;
+                                if (P.wave != nullptr && i == P.i_ext) P.wave[jf] = oP;
+                            }
+                            if (!FAST) {
+                                if (jf == 1) { oP1 = oP; oQ1 = oQ; }
+                                if (jf == 2) {   // pole row 0 from rows 1, 2
+                                    const double2 p0 = masked(interior_col, pole_value(P.even, oP1, oP));
+                                    const double2 q0 = masked(interior_col, pole_value(P.even, oQ1, oQ));
+                                    if (writer) {
+                                        P.phi_out[i] = p0;
+                                        P.pi_out[i] = q0;
+                                        if (P.wave != nullptr && i == P.i_ext) P.wave[0] = p0;
+                                    }
+                                }
+                                if (jf == nth - 2) {   // last pole row from rows nth-2, nth-3
+                                    const double2 pl = masked(interior_col, pole_value(P.even, oP, oPp));
+                                    const double2 ql = masked(interior_col, pole_value(P.even, oQ, oQp));
+                                    if (writer) {
+                                        P.phi_out[static_cast<size_t>(nth - 1) * ld + i] = pl;
+                                        P.pi_out[static_cast<size_t>(nth - 1) * ld + i] = ql;
+                                        if (P.wave != nullptr && i == P.i_ext) P.wave[nth - 1] = pl;
+                                    }
+                                }
+                                oPp = oP;
+                                oQp = oQ;
                             }
                         }
-                        oPp = oP;
-                        oQp = oQ;
                     }
                 }
             }
         }
-    }
+    };
+
+    const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
+                          jlo >= 4 && jlo + SEG <= nth - 2;
+    if (interior)   // uniform per wave
+        body(std::true_type{});
+    else
+        body(std::false_type{});
 }
 
 // Compact source pass: F on the windows near the particle for a batch of

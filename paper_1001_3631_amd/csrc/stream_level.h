@@ -20,12 +20,14 @@ constexpr int kPrefetchRows = TEUK_PREFETCH_ROWS;
 namespace {
 
 // Cross-lane moves with DPP wave shifts (no LDS traffic): from_next gives lane
-// l the value of lane l+1 (lane 63 keeps its own), from_prev the value of lane
-// l-1 (lane 0 keeps its own).
+// l the value of lane l+1 (lane 63 gets zero), from_prev the value of lane
+// l-1 (lane 0 gets zero).  Lanes 0 and 63 are halo lanes whose results are
+// never stored, so the fill value is free; zero fill (bound_ctrl) needs no
+// copy of the old value in front of each move.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double2 from_next(double2 v) {
@@ -89,9 +91,18 @@ struct LevelArgs {
 // Parameters are taken by value: with references the compiler must assume
 // that the output stores may alias them and re-reads fields after each store.
 // rows is the kernel's __restrict__ argument where it has one (scalar loads).
-template <int NROW, bool IN_LDS, bool OUT_LDS, int PREFETCH = kPrefetchRows>
+//
+// FAST_ROWS > 0 is the interior form, which the caller may choose when
+// hi - lo == FAST_ROWS, lo >= 4, hi <= nth - 2 and every lane is an interior
+// column (1 <= i <= nr - 2): every row and half row is then in range and no
+// pole or ghost row is touched, so those tests become constants.  The
+// arithmetic on every point is the same in both forms.
+template <int NROW, bool IN_LDS, bool OUT_LDS, int PREFETCH = kPrefetchRows, int FAST_ROWS = 0>
 __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs A, const RCol rn,
                                              const RCol rh, const ThetaRow* __restrict__ rows) {
+    constexpr bool FAST = FAST_ROWS > 0;
+    static_assert(FAST_ROWS <= NROW, "interior rows exceed the window");
+    constexpr int NT = FAST ? FAST_ROWS + 4 : NROW + 4;   // input rows lo-2 .. hi+1
     const int nth = P.nth;
     const int ld = P.ld;
     const int i = A.i;
@@ -127,26 +138,26 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
     double2 fP[NROW + 4], fQ[NROW + 4];
     const int icl = min(max(i, 0), P.nr - 1);
     auto fetch = [&](int t) {
-        const int jc = min(max(lo - 2 + t, 0), nth - 1);
+        const int jc = FAST ? lo - 2 + t : min(max(lo - 2 + t, 0), nth - 1);
         fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
         fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
     };
 #pragma unroll
-    for (int t = 0; t < PF && t < NROW + 4; ++t) fetch(t);
+    for (int t = 0; t < PF && t < NT; ++t) fetch(t);
 
 #pragma unroll
-    for (int t = 0; t < NROW + 4; ++t) {
-        if (!IN_LDS && t + PF < NROW + 4) fetch(t + PF);
+    for (int t = 0; t < NT; ++t) {
+        if (!IN_LDS && t + PF < NT) fetch(t + PF);
         const int jj = lo - 2 + t;
-        if (jj <= hi + 1) {
+        if (FAST || jj <= hi + 1) {
             // ---- row jj of the input level and its column sums/differences ----
             double2 p = z, q = z;
             if (IN_LDS) {
-                if (jj >= 0 && jj < nth) {
+                if (FAST || (jj >= 0 && jj < nth)) {
                     p = A.lp[(jj - A.lbase) * 64 + lane];
                     q = A.lq[(jj - A.lbase) * 64 + lane];
                 }
-            } else if (jj >= 0 && jj < nth && in_col) {
+            } else if (FAST || (jj >= 0 && jj < nth && in_col)) {
                 p = fP[t];
                 q = fQ[t];
             }
@@ -163,7 +174,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                 const int jh = jj - 1;
                 hP[t - 1] = z;
                 hQ[t - 1] = z;
-                if (jh >= 1 && jh <= nth - 2) {
+                if (FAST || (jh >= 1 && jh <= nth - 2)) {
                     const ThetaRow R = rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                     const double2 F = src_lookup(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh);
@@ -174,7 +185,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                     hP[t - 1] = pole_value(P.even, hP[t - 2], hP[t - 3]);
                     hQ[t - 1] = pole_value(P.even, hQ[t - 2], hQ[t - 3]);
                 }
-                if (jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
+                if (!FAST && jh == 2 && t >= 5) {   // pole row 0 of the half step, now that rows 1, 2 exist
                     hP[t - 3] = pole_value(P.even, hP[t - 2], hP[t - 1]);
                     hQ[t - 3] = pole_value(P.even, hQ[t - 2], hQ[t - 1]);
                     gP[t - 3] = from_prev(hP[t - 3]);
@@ -187,10 +198,10 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
             // ---- full step (lw2) at (i, jf), jf = jj - 2 ----
             if (t >= 4) {
                 const int jf = jj - 2;
-                if (jf >= lo && jf < hi) {
+                if (FAST || (jf >= lo && jf < hi)) {
                     double2 oP = z, oQ = z;
-                    const bool pole = (jf == 0) || (jf == nth - 1);
-                    if (!pole && interior_col) {
+                    const bool pole = !FAST && ((jf == 0) || (jf == nth - 1));
+                    if (FAST || (!pole && interior_col)) {
                         const ThetaRow R = rows[jf];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                         const double2 F = src_lookup(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf);
@@ -206,29 +217,31 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                         if (P.ko_c != 0.0) {
                             const double sg = P.even ? 1.0 : -1.0;
                             // rows jf-2 .. jf+2; ghost rows -1 and nth reflect row 1 / nth-2
-                            const double2 pm2 = (jf == 1) ? c_scale(sg, uP[t - 2]) : uP[t - 4];
-                            const double2 qm2 = (jf == 1) ? c_scale(sg, uQ[t - 2]) : uQ[t - 4];
-                            const double2 pp2 = (jf == nth - 2) ? c_scale(sg, uP[t - 2]) : uP[t];
-                            const double2 qp2 = (jf == nth - 2) ? c_scale(sg, uQ[t - 2]) : uQ[t];
+                            const bool lo_ghost = !FAST && jf == 1;
+                            const bool hi_ghost = !FAST && jf == nth - 2;
+                            const double2 pm2 = lo_ghost ? c_scale(sg, uP[t - 2]) : uP[t - 4];
+                            const double2 qm2 = lo_ghost ? c_scale(sg, uQ[t - 2]) : uQ[t - 4];
+                            const double2 pp2 = hi_ghost ? c_scale(sg, uP[t - 2]) : uP[t];
+                            const double2 qp2 = hi_ghost ? c_scale(sg, uQ[t - 2]) : uQ[t];
                             oP = ko_apply(oP, P.ko_c, pm2, uP[t - 3], uP[t - 2], uP[t - 1], pp2);
                             oQ = ko_apply(oQ, P.ko_c, qm2, uQ[t - 3], uQ[t - 2], uQ[t - 1], qp2);
                         }
                     }
                     if (!pole) {
                         store(jf, oP, oQ);
-                        if (jf == 1) { oP1 = oP; oQ1 = oQ; }
-                        if (jf == 2 && lo == 0) {   // pole row 0 from rows 1, 2
-                            const double2 p0 = pole_value(P.even, oP1, oP);
-                            const double2 q0 = pole_value(P.even, oQ1, oQ);
-                            store(0, interior_col ? p0 : z, interior_col ? q0 : z);
+                        if (!FAST) {
+                            if (jf == 1) { oP1 = oP; oQ1 = oQ; }
+                            if (jf == 2 && lo == 0) {   // pole row 0 from rows 1, 2
+                                store(0, masked(interior_col, pole_value(P.even, oP1, oP)),
+                                      masked(interior_col, pole_value(P.even, oQ1, oQ)));
+                            }
+                            if (jf == nth - 2 && hi == nth) {   // last pole row from rows nth-2, nth-3
+                                store(nth - 1, masked(interior_col, pole_value(P.even, oP, oPp)),
+                                      masked(interior_col, pole_value(P.even, oQ, oQp)));
+                            }
+                            oPp = oP;
+                            oQp = oQ;
                         }
-                        if (jf == nth - 2 && hi == nth) {   // last pole row from rows nth-2, nth-3
-                            const double2 pl = pole_value(P.even, oP, oPp);
-                            const double2 ql = pole_value(P.even, oQ, oQp);
-                            store(nth - 1, interior_col ? pl : z, interior_col ? ql : z);
-                        }
-                        oPp = oP;
-                        oQp = oQ;
                     }
                 }
             }
