@@ -22,6 +22,8 @@
 // t_n + dt/2); each wave writes its partial sum, reduced in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "lw_point.h"
 #include "stream_level.h"   // wave shifts (from_next, from_prev)
@@ -102,21 +104,30 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     const RCol rn = load_rcol(P.rnode, P.rpitch, min(max(i, 0), P.nr - 1));
     const RCol rh = load_rcol(P.rhalf, P.rpitch, min(max(i, 0), P.nr - 2));
 
+    double dA = 0.0;
+
+    // Interior form (the same arithmetic on every point): all 64 columns
+    // interior, the segment not the last, and every row the stages touch in
+    // [3, nth-4], away from the pole rows and the rows they fold into
+    // (jlo >= 7, jhi <= nth - 7).  Its range, fold and column tests are
+    // constants, so the unrolled window carries no selects for them.
+    auto body = [&](auto interior_tag) {
+    constexpr bool FAST = decltype(interior_tag)::value;
+    const int jhi_ = FAST ? jlo + SEG : jhi;
     double2 lP[NT], lQ[NT];          // lambda^{n+1}, own column, row jlo-4+t
     double2 mP[NT], mQ[NT];          // mu (after the boundary transpose)
     double2 nQ[NT], nD[NT], nDQ[NT], nC[NT], nW[NT];   // node-level sources
     double2 hP[NT], hQ[NT];          // half-level lambda at i+1/2 (unfolded)
     double2 yW[NT], cC[NT], qb[NT], dp[NT], dq[NT];    // half-level sources
-    double dA = 0.0;
 
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
         const int jj = jlo - 4 + it;
-        if (jj > jhi + 5) continue;
+        if (FAST ? it > SEG + 9 : jj > jhi + 5) continue;
         // ---- 1. load lambda^{n+1}(i, jj) ----
         {
             double2 p = cz(), q = cz();
-            if (jj >= 0 && jj < nth && in_col) {
+            if (FAST || (jj >= 0 && jj < nth && in_col)) {
                 p = P.lam_phi[static_cast<size_t>(jj) * ld + i];
                 q = P.lam_pi[static_cast<size_t>(jj) * ld + i];
             }
@@ -128,11 +139,11 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const int r = jj - 2;
             const int k = it - 2;
             double2 p = cz(), q = cz();
-            const bool interior_row = (r >= 1) && (r <= nth - 2);
-            if (interior_row && interior_col) {
+            const bool interior_row = FAST || ((r >= 1) && (r <= nth - 2));
+            if (FAST || (interior_row && interior_col)) {
                 p = lP[k];
                 q = lQ[k];
-                if (P.even) {
+                if (!FAST && P.even) {
                     if (r == 1 && it >= 3) { p = axpy(four_thirds, lP[k - 1], p); q = axpy(four_thirds, lQ[k - 1], q); }
                     if (r == 2 && it >= 4) { p = axpy(-third, lP[k - 2], p); q = axpy(-third, lQ[k - 2], q); }
                     if (r == nth - 2) { p = axpy(four_thirds, lP[k + 1], p); q = axpy(four_thirds, lQ[k + 1], q); }
@@ -142,7 +153,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             mP[k] = p;
             mQ[k] = q;
             nQ[k] = nD[k] = nDQ[k] = nC[k] = nW[k] = cz();
-            if (interior_row && interior_col) {
+            if (FAST || (interior_row && interior_col)) {
                 const ThetaRow R = rows[r];
                 const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi' = Phi + dt (Pi~ - b dPhi);  Pi' = Pi + dt (b dPi + S),
@@ -155,7 +166,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 const double2 c0q = cmul_conj(c.c0, q);
                 nC[k] = make_double2(dt * c0q.x, dt * c0q.y);                         // -> Phi~ (row r)
                 nW[k] = make_double2(dt * c.w * q.x, dt * c.w * q.y);                 // -> Ang^T
-                if (P.fn != nullptr && r >= jlo && r < jhi && writer) {
+                if (P.fn != nullptr && r >= jlo && r < jhi_ && writer) {
                     const double2 F = src_at(P.fn, org.z, org.w, P.win_r, P.win_t, i, r);
                     dA = fma(dt, re_dot_conj(q, F), dA);
                 }
@@ -166,11 +177,11 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const int r1 = jj - 3;
             const int k = it - 3;
             double2 ptil = cz();
-            if (r1 >= 0 && r1 < nth) {
+            if (FAST || (r1 >= 0 && r1 < nth)) {
                 ptil = nC[k];
-                if (r1 - 1 >= 1) ptil = axpy(ang_weights(rows[r1 - 1]).alpha, nW[k - 1], ptil);
-                if (r1 >= 1 && r1 <= nth - 2) ptil = axpy(ang_weights(rows[r1]).beta, nW[k], ptil);
-                if (r1 + 1 <= nth - 2) ptil = axpy(ang_weights(rows[r1 + 1]).gamma, nW[k + 1], ptil);
+                if (FAST || r1 - 1 >= 1) ptil = axpy(ang_weights(rows[r1 - 1]).alpha, nW[k - 1], ptil);
+                if (FAST || (r1 >= 1 && r1 <= nth - 2)) ptil = axpy(ang_weights(rows[r1]).beta, nW[k], ptil);
+                if (FAST || r1 + 1 <= nth - 2) ptil = axpy(ang_weights(rows[r1 + 1]).gamma, nW[k + 1], ptil);
             }
             // contributions of node i to its right half (i+1/2) and left half (i-1/2)
             const double2 a = make_double2(0.5 * ptil.x, 0.5 * ptil.y);
@@ -179,7 +190,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const double2 dqv = make_double2(nDQ[k].x * inv_hr, nDQ[k].y * inv_hr);
             const double2 leftP = c_sub(a, d), leftQ = c_sub(aq, dqv);
             const double2 nbP = from_next(leftP), nbQ = from_next(leftQ);   // node i+1's left part
-            if (has_half) {
+            if (FAST || has_half) {
                 hP[k] = c_add(c_add(a, d), nbP);
                 hQ[k] = c_add(c_add(aq, dqv), nbQ);
             } else {
@@ -192,9 +203,9 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const int r2 = jj - 5;
             const int k = it - 5;
             yW[k] = cC[k] = qb[k] = dp[k] = dq[k] = cz();
-            if (r2 >= 1 && r2 <= nth - 2 && has_half) {
+            if (FAST || (r2 >= 1 && r2 <= nth - 2 && has_half)) {
                 double2 p = hP[k], q = hQ[k];
-                if (P.even) {
+                if (!FAST && P.even) {
                     if (r2 == 1) { p = axpy(four_thirds, hP[k - 1], p); q = axpy(four_thirds, hQ[k - 1], q); }
                     if (r2 == 2) { p = axpy(-third, hP[k - 2], p); q = axpy(-third, hQ[k - 2], q); }
                     if (r2 == nth - 2) { p = axpy(four_thirds, hP[k + 1], p); q = axpy(four_thirds, hQ[k + 1], q); }
@@ -211,7 +222,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 const double2 mrq = cmul_conj(c.mr, q);
                 dp[k] = make_double2(hdt * fma(-c.b, p.x, mrq.x), hdt * fma(-c.b, p.y, mrq.y));
                 dq[k] = make_double2(hdt * c.b * q.x, hdt * c.b * q.y);
-                if (P.fh != nullptr && r2 >= jlo && r2 < jhi && writer) {
+                if (P.fh != nullptr && r2 >= jlo && r2 < jhi_ && writer) {
                     const double2 F = src_at(P.fh, org.x, org.y, P.win_r, P.win_t, i, r2);
                     dA = fma(hdt, re_dot_conj(q, F), dA);
                 }
@@ -222,11 +233,11 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const int r3 = jj - 6;
             const int k = it - 6;
             double2 pb = cz();
-            if (r3 >= 0 && r3 < nth) {
+            if (FAST || (r3 >= 0 && r3 < nth)) {
                 pb = cC[k];
-                if (r3 - 1 >= 1) pb = axpy(ang_weights(rows[r3 - 1]).alpha, yW[k - 1], pb);
-                if (r3 >= 1 && r3 <= nth - 2) pb = axpy(ang_weights(rows[r3]).beta, yW[k], pb);
-                if (r3 + 1 <= nth - 2) pb = axpy(ang_weights(rows[r3 + 1]).gamma, yW[k + 1], pb);
+                if (FAST || r3 - 1 >= 1) pb = axpy(ang_weights(rows[r3 - 1]).alpha, yW[k - 1], pb);
+                if (FAST || (r3 >= 1 && r3 <= nth - 2)) pb = axpy(ang_weights(rows[r3]).beta, yW[k], pb);
+                if (FAST || r3 + 1 <= nth - 2) pb = axpy(ang_weights(rows[r3 + 1]).gamma, yW[k + 1], pb);
             }
             // half i+1/2 gives its left node (i) 1/2 avg - diff/h, its right node (i+1) 1/2 avg + diff/h
             const double2 hpP = make_double2(0.5 * pb.x, 0.5 * pb.y);
@@ -235,10 +246,10 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             const double2 hdQ = make_double2(dq[k].x * inv_hr, dq[k].y * inv_hr);
             const double2 rightP = c_add(hpP, hdP), rightQ = c_add(hpQ, hdQ);
             const double2 fromLeftP = from_prev(rightP), fromLeftQ = from_prev(rightQ);
-            if (r3 >= jlo && r3 < jhi && writer) {
-                double2 oP = c_add(c_sub(hpP, hdP), (i >= 1) ? fromLeftP : cz());
-                double2 oQ = c_add(c_sub(hpQ, hdQ), (i >= 1) ? fromLeftQ : cz());
-                if (interior_col) {
+            if (r3 >= jlo && r3 < jhi_ && writer) {
+                double2 oP = c_add(c_sub(hpP, hdP), (FAST || i >= 1) ? fromLeftP : cz());
+                double2 oQ = c_add(c_sub(hpQ, hdQ), (FAST || i >= 1) ? fromLeftQ : cz());
+                if (FAST || interior_col) {
                     // identity part and the dissipation transpose (mu is zero off the interior)
                     oP = c_add(oP, mP[k]);
                     oQ = c_add(oQ, mQ[k]);
@@ -246,7 +257,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                         const double sg = P.even ? 1.0 : -1.0;
                         double2 kp = ko_apply(cz(), -1.0, mP[k - 2], mP[k - 1], mP[k], mP[k + 1], mP[k + 2]);
                         double2 kq = ko_apply(cz(), -1.0, mQ[k - 2], mQ[k - 1], mQ[k], mQ[k + 1], mQ[k + 2]);
-                        if (r3 == 1 || r3 == nth - 2) {   // ghost row reflected onto this row
+                        if (!FAST && (r3 == 1 || r3 == nth - 2)) {   // ghost row reflected onto this row
                             kp = axpy(sg, mP[k], kp);
                             kq = axpy(sg, mQ[k], kq);
                         }
@@ -260,6 +271,14 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             }
         }
     }
+    };
+
+    const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
+                          jlo >= 7 && jlo + SEG <= nth - 7;
+    if (interior)   // uniform per wave
+        body(std::true_type{});
+    else
+        body(std::false_type{});
     // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
     if (P.dA_part != nullptr) {
         double v = dA;
