@@ -34,6 +34,25 @@ __device__ __forceinline__ RCol load_rcol(const double* __restrict__ tab, int pi
     return r;
 }
 
+// x^(-1/2) for a positive normal x: the hardware estimate y refined by one
+// second-order step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...,
+// e = 1 - x y^2.  (The library rsqrt adds a class test for 0, inf and NaN;
+// the arguments here never are.)
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// 1/x for a positive normal x: the hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r) (within an ulp or two of the
+// rounded quotient; the IEEE division adds scaling and a final correction).
+__device__ __forceinline__ double recip_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Coefficient fields at one point.
 struct Coef {
     double b, w;
@@ -48,7 +67,7 @@ struct Coef {
 // a != 0 the term is an exact signed zero, so both forms agree bitwise.)
 __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin2, bool kerr) {
     const double sig2 = fma(-r.a2d, sin2, r.q2);
-    const double g = rsqrt(sig2);
+    const double g = rsqrt_pos(sig2);
     const double g2 = g * g;
     const double g4 = g2 * g2;
     Coef c;
@@ -60,7 +79,7 @@ __device__ __forceinline__ Coef coef_at(const RCol& r, double cos_th, double sin
     c.c0.y = r.c0_im * g2;
     double num = r.mr_p;
     if (kerr) {
-        const double inv_qs = 1.0 / fma(sig2, g, r.q);   // 1/(q + Sigma), Sigma = Sigma^2 g
+        const double inv_qs = recip_pos(fma(sig2, g, r.q));   // 1/(q + Sigma), Sigma = Sigma^2 g
         num = fma(-r.a2d * sin2, fma(r.mr_k1, inv_qs, r.mr_k2), num);
     }
     c.mr.x = num * g4;
