@@ -16,8 +16,12 @@ namespace teuk {
 // 64 - 2K owner columns.  Levels 1..K-1 stay in this wave's LDS buffer; only
 // level K is written to HBM.  Every point goes through stream_level, so a
 // block is bitwise identical to K single iterations.  FAST: every level is
-// interior (see stream_level) and has SEG + 4(K - L) rows.
-template <int SEG, int K, int L, bool FAST>
+// interior (see stream_level) and has SEG + 4(K - L) rows.  SRC: some level's
+// source window meets the wave (else no level does lookups).  The lookups
+// are read where used: fetching them ahead, as the single-step kernel does,
+// would take this kernel past 256 VGPRs and every wave to one per SIMD, for
+// the few waves that have them.
+template <int SEG, int K, int L, bool FAST, bool SRC>
 __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, int jlo, int jhi,
                                              const RCol& rn, const RCol& rh,
                                              const ThetaRow* __restrict__ rows) {
@@ -30,8 +34,8 @@ __device__ __forceinline__ void block_levels(const StepParams& P, LevelArgs& A, 
     A.org = make_int4(0, 0, 0, 0);
     if (P.org != nullptr) A.org = P.org[L - 1];
     A.wave = P.wave ? P.wave + static_cast<size_t>(L - 1) * P.nth : nullptr;
-    stream_level<NROW, (L > 1), (L < K), kPrefetchRows, FAST ? SEG + 4 * (K - L) : 0>(P, A, rn, rh, rows);
-    if constexpr (L < K) block_levels<SEG, K, L + 1, FAST>(P, A, jlo, jhi, rn, rh, rows);
+    stream_level<NROW, (L > 1), (L < K), kPrefetchRows, FAST ? SEG + 4 * (K - L) : 0, SRC>(P, A, rn, rh, rows);
+    if constexpr (L < K) block_levels<SEG, K, L + 1, FAST, SRC>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 template <int SEG, int K>
@@ -61,10 +65,25 @@ __global__ void __launch_bounds__(64) lw_block_kernel(StepParams P, const ThetaR
     const int i0 = strip * (64 - 2 * K) - K;
     const bool interior = i0 >= 1 && i0 + 63 <= P.nr - 2 && seg != P.nseg - 1 &&
                           jlo - 2 * (K - 1) >= 4 && jhi + 2 * (K - 1) <= P.nth - 2;
-    if (interior)   // uniform per wave
-        block_levels<SEG, K, 1, true>(P, A, jlo, jhi, rn, rh, rows);
+    // does any level's source window meet the wave's widest region (columns
+    // of all 64 lanes, rows of level 1 and the half rows around them)?
+    // (the origins are those the levels' lookups use)
+    // The launcher sets both window tables or neither.
+    bool src = false;
+    if (P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0) {
+        for (int l = 0; l < K; ++l) {
+            const int4 o = (P.org != nullptr) ? P.org[l] : make_int4(0, 0, 0, 0);
+            src = src ||
+                  window_meets(o, false, P.win_r, P.win_t, i0, jlo - 2 * (K - 1) - 1, jhi + 2 * (K - 1)) ||
+                  window_meets(o, true, P.win_r, P.win_t, i0, jlo - 2 * (K - 1), jhi + 2 * (K - 1) - 1);
+        }
+    }
+    if (src)   // uniform per wave
+        block_levels<SEG, K, 1, false, true>(P, A, jlo, jhi, rn, rh, rows);
+    else if (interior)
+        block_levels<SEG, K, 1, true, false>(P, A, jlo, jhi, rn, rh, rows);
     else
-        block_levels<SEG, K, 1, false>(P, A, jlo, jhi, rn, rh, rows);
+        block_levels<SEG, K, 1, false, false>(P, A, jlo, jhi, rn, rh, rows);
 }
 
 bool valid_block(int seg, int k) {

@@ -31,7 +31,8 @@ struct StepParams {
     int kerr;                   // a != 0
     int i_ext;
     double2* wave;              // nth entries for this iteration, or null
-    // source windows of this iteration (null when no source)
+    // source windows of this iteration: both set, or both null when there is
+    // no source
     const double2* fh;          // half points: [win_t][win_r]
     const double2* fn;          // nodes: [win_t][win_r]
     const int4* org;            // window origins: half (col0,row0), node (col0,row0)

@@ -59,12 +59,16 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
 
     // The wave's rows and columns are either all interior (every row and
     // half row in range, no pole or ghost row, every lane an interior
-    // column: most items) or not.  The body is instantiated for both cases;
-    // in the interior one the range, pole and column tests are constants, so
-    // the unrolled window carries no selects or copies for them.  Both run
-    // the same arithmetic on every point.
-    auto body = [&](auto interior_tag) {
+    // column: most items) or not, and the wave either meets a source window
+    // or not (window_meets).  The body is instantiated for interior waves
+    // without the source, other waves without it, and waves with it.  In the
+    // interior form the range, pole and column tests are constants, so the
+    // unrolled window carries no selects or copies for them; without the
+    // source there are no lookups (F = 0, as a lookup outside the window
+    // gives).  All run the same arithmetic on every point.
+    auto body = [&](auto interior_tag, auto src_tag) {
         constexpr bool FAST = decltype(interior_tag)::value;
+        constexpr bool SRC = decltype(src_tag)::value;
         // rows of u^n the segment reads: jlo-2 .. jhi+1 (t < NT)
         constexpr int NT = FAST ? SEG + 4 : SEG + 6;
         double2 uP[SEG + 6], uQ[SEG + 6];     // u^n, own column, rows jlo-2+t
@@ -81,10 +85,25 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
         constexpr int PF = kPrefetchRows;
         double2 fP[SEG + 6], fQ[SEG + 6];
         const int icl = min(max(i, 0), P.nr - 1);
+        // With the source, its values for the half step of row jlo-3+t and
+        // the full step of row jlo-4+t are fetched with row t, at clamped
+        // window indices, and masked where used (a lookup that waits at
+        // once would also wait for every load issued before it).
+        double2 fFh[SEG + 6], fFn[SEG + 6];
+        const int dch = i - org.x, dcn = i - org.z;
+        const bool colh = static_cast<unsigned>(dch) < static_cast<unsigned>(P.win_r);
+        const bool coln = static_cast<unsigned>(dcn) < static_cast<unsigned>(P.win_r);
+        const int dchc = min(max(dch, 0), P.win_r - 1), dcnc = min(max(dcn, 0), P.win_r - 1);
         auto fetch = [&](int t) {
             const int jc = FAST ? jlo - 2 + t : min(max(jlo - 2 + t, 0), nth - 1);
             fP[t] = P.phi[static_cast<size_t>(jc) * ld + icl];
             fQ[t] = P.pi[static_cast<size_t>(jc) * ld + icl];
+            if (SRC) {
+                const int rh_ = min(max(jlo - 3 + t - org.y, 0), P.win_t - 1);
+                const int rn_ = min(max(jlo - 4 + t - org.w, 0), P.win_t - 1);
+                fFh[t] = P.fh[rh_ * P.win_r + dchc];
+                fFn[t] = P.fn[rn_ * P.win_r + dcnc];
+            }
         };
 #pragma unroll
         for (int t = 0; t < PF && t < NT; ++t) fetch(t);
@@ -116,7 +135,10 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
                     if (FAST || (jh >= 1 && jh <= nth - 2)) {
                         const ThetaRow R = rows[jh];
                         const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
-                        const double2 F = src_lookup(P.fh, org.x, org.y, P.win_r, P.win_t, i, jh);
+                        const double2 F =
+                            SRC ? masked(colh && static_cast<unsigned>(jh - org.y) < static_cast<unsigned>(P.win_t),
+                                         fFh[t])
+                                : z;
                         lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
                                  dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
                                  c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
@@ -143,7 +165,10 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
                         if (FAST || (!pole && interior_col)) {
                             const ThetaRow R = rows[jf];
                             const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
-                            const double2 F = src_lookup(P.fn, org.z, org.w, P.win_r, P.win_t, i, jf);
+                            const double2 F =
+                                SRC ? masked(coln && static_cast<unsigned>(jf - org.w) < static_cast<unsigned>(P.win_t),
+                                             fFn[t])
+                                    : z;
                             // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
                             const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
                             const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
@@ -204,10 +229,17 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
 
     const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
                           jlo >= 4 && jlo + SEG <= nth - 2;
-    if (interior)   // uniform per wave
-        body(std::true_type{});
+    const int i0 = strip * 62 - 1;
+    // (the launcher sets both window tables or neither)
+    const bool src = P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
+                     (window_meets(org, false, P.win_r, P.win_t, i0, jlo - 1, jhi) ||
+                      window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
+    if (src)   // uniform per wave
+        body(std::false_type{}, std::true_type{});
+    else if (interior)
+        body(std::true_type{}, std::false_type{});
     else
-        body(std::false_type{});
+        body(std::false_type{}, std::false_type{});
 }
 
 // Compact source pass: F on the windows near the particle for a batch of

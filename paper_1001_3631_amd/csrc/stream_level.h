@@ -1,5 +1,5 @@
 // Device helpers shared by the stepping kernels: wave shifts, the source
-// window lookup, the XCD-aware work-item order, and stream_level, one level
+// window test, the XCD-aware work-item order, and stream_level, one level
 // of the streaming Lax-Wendroff stencil (Sec. 3.2, Eqs. (lw1), (lw2)) used
 // by the temporally blocked and batched kernels.  Internal to the library.
 #pragma once
@@ -37,16 +37,27 @@ __device__ __forceinline__ double2 from_prev(double2 v) {
     return make_double2(dpp_move<0x138>(v.x), dpp_move<0x138>(v.y));   // wave_shr:1
 }
 
-
-
-__device__ __forceinline__ double2 src_lookup(const double2* __restrict__ tab, int c0, int r0,
-                                              int win_r, int win_t, int col, int row) {
-    if (tab == nullptr) return make_double2(0.0, 0.0);
+// Source value at (col, row) of a window table with origin (c0, r0), zero
+// outside it.
+__device__ __forceinline__ double2 window_value(const double2* __restrict__ tab, int c0, int r0, int win_r,
+                                                int win_t, int col, int row) {
     const unsigned dc = static_cast<unsigned>(col - c0);
     const unsigned dr = static_cast<unsigned>(row - r0);
-    if (dc < static_cast<unsigned>(win_r) && dr < static_cast<unsigned>(win_t))
-        return tab[dr * win_r + dc];
+    if (dc < static_cast<unsigned>(win_r) && dr < static_cast<unsigned>(win_t)) return tab[dr * win_r + dc];
     return make_double2(0.0, 0.0);
+}
+
+// Whether the window [c0, c0 + win_r) x [r0, r0 + win_t) meets the columns
+// [i0, i0 + 63] and rows [ja, jb] of a wave.  A wave that meets no window of
+// its iteration takes the forms of its body without source lookups: a lookup
+// is a conditional load, and the wait for its result (which cannot be told
+// apart from the wait for every load issued before it) would also wait for
+// the rows prefetched ahead, on every row.
+__device__ __forceinline__ bool window_meets(int4 org2, bool node, int win_r, int win_t, int i0, int ja,
+                                             int jb) {
+    const int c0 = node ? org2.z : org2.x;
+    const int r0 = node ? org2.w : org2.y;
+    return c0 <= i0 + 63 && i0 < c0 + win_r && r0 <= jb && ja < r0 + win_t;
 }
 
 // Workgroups are handed to the 8 XCDs round robin; renumber them so that each
@@ -95,9 +106,12 @@ struct LevelArgs {
 // FAST_ROWS > 0 is the interior form, which the caller may choose when
 // hi - lo == FAST_ROWS, lo >= 4, hi <= nth - 2 and every lane is an interior
 // column (1 <= i <= nr - 2): every row and half row is then in range and no
-// pole or ghost row is touched, so those tests become constants.  The
-// arithmetic on every point is the same in both forms.
-template <int NROW, bool IN_LDS, bool OUT_LDS, int PREFETCH = kPrefetchRows, int FAST_ROWS = 0>
+// pole or ghost row is touched, so those tests become constants.  SRC adds
+// the source lookups (A.fh, A.fn non-null; the caller chooses it when a
+// window of the level meets the wave, window_meets).  Without it F = 0,
+// which is what a lookup outside the window gives.  The arithmetic on every
+// point is the same in all forms.
+template <int NROW, bool IN_LDS, bool OUT_LDS, int PREFETCH = kPrefetchRows, int FAST_ROWS = 0, bool SRC = false>
 __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs A, const RCol rn,
                                              const RCol rh, const ThetaRow* __restrict__ rows) {
     constexpr bool FAST = FAST_ROWS > 0;
@@ -177,7 +191,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                 if (FAST || (jh >= 1 && jh <= nth - 2)) {
                     const ThetaRow R = rows[jh];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
-                    const double2 F = src_lookup(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh);
+                    const double2 F = SRC ? window_value(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh) : z;
                     lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
                              dP[t - 1], dQ[t - 1], F, 0.5 * P.dt, P.inv_hr, c_scale(0.5, sP[t - 1]),
                              c_scale(0.5, sQ[t - 1]), hP[t - 1], hQ[t - 1]);
@@ -204,7 +218,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                     if (FAST || (!pole && interior_col)) {
                         const ThetaRow R = rows[jf];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
-                        const double2 F = src_lookup(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf);
+                        const double2 F = SRC ? window_value(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf) : z;
                         // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
                         const double2 sPm = c_add(hP[t - 3], gP[t - 3]);
                         const double2 sP0 = c_add(hP[t - 2], gP[t - 2]);
