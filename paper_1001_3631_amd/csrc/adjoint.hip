@@ -111,8 +111,12 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     // [3, nth-4], away from the pole rows and the rows they fold into
     // (jlo >= 7, jhi <= nth - 7).  Its range, fold and column tests are
     // constants, so the unrolled window carries no selects for them.
-    auto body = [&](auto interior_tag) {
+    // SRC: a source window meets the wave's output rows and columns; without
+    // it the wave's source terms are all zero and are skipped.  (A lookup is a
+    // load used at once, and its wait also waits for every load before it.)
+    auto body = [&](auto interior_tag, auto src_tag) {
     constexpr bool FAST = decltype(interior_tag)::value;
+    constexpr bool SRC = decltype(src_tag)::value;
     const int jhi_ = FAST ? jlo + SEG : jhi;
     double2 lP[NT], lQ[NT];          // lambda^{n+1}, own column, row jlo-4+t
     double2 mP[NT], mQ[NT];          // mu (after the boundary transpose)
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 const double2 c0q = cmul_conj(c.c0, q);
                 nC[k] = make_double2(dt * c0q.x, dt * c0q.y);                         // -> Phi~ (row r)
                 nW[k] = make_double2(dt * c.w * q.x, dt * c.w * q.y);                 // -> Ang^T
-                if (P.fn != nullptr && r >= jlo && r < jhi_ && writer) {
+                if (SRC && r >= jlo && r < jhi_ && writer) {
                     const double2 F = src_at(P.fn, org.z, org.w, P.win_r, P.win_t, i, r);
                     dA = fma(dt, re_dot_conj(q, F), dA);
                 }
@@ -222,7 +226,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 const double2 mrq = cmul_conj(c.mr, q);
                 dp[k] = make_double2(hdt * fma(-c.b, p.x, mrq.x), hdt * fma(-c.b, p.y, mrq.y));
                 dq[k] = make_double2(hdt * c.b * q.x, hdt * c.b * q.y);
-                if (P.fh != nullptr && r2 >= jlo && r2 < jhi_ && writer) {
+                if (SRC && r2 >= jlo && r2 < jhi_ && writer) {
                     const double2 F = src_at(P.fh, org.x, org.y, P.win_r, P.win_t, i, r2);
                     dA = fma(hdt, re_dot_conj(q, F), dA);
                 }
@@ -275,10 +279,21 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
 
     const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
                           jlo >= 7 && jlo + SEG <= nth - 7;
-    if (interior)   // uniform per wave
-        body(std::true_type{});
-    else
-        body(std::false_type{});
+    // (the launcher sets both window tables or neither)
+    const int i0 = strip * 62 - 1;
+    const bool src = P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
+                     (window_meets(org, false, P.win_r, P.win_t, i0, jlo, jhi - 1) ||
+                      window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
+    if (src) {   // uniform per wave
+        if (interior)
+            body(std::true_type{}, std::true_type{});
+        else
+            body(std::false_type{}, std::true_type{});
+    } else if (interior) {
+        body(std::true_type{}, std::false_type{});
+    } else {
+        body(std::false_type{}, std::false_type{});
+    }
     // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
     if (P.dA_part != nullptr) {
         double v = dA;

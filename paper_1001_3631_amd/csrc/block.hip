@@ -78,12 +78,18 @@ __global__ void __launch_bounds__(64) lw_block_kernel(StepParams P, const ThetaR
                   window_meets(o, true, P.win_r, P.win_t, i0, jlo - 2 * (K - 1), jhi + 2 * (K - 1) - 1);
         }
     }
-    if (src)   // uniform per wave
-        block_levels<SEG, K, 1, false, true>(P, A, jlo, jhi, rn, rh, rows);
-    else if (interior)
+    // (uniform per wave; each wave runs alone on its SIMD on small grids, so
+    // the source waves get the interior form too)
+    if (src) {
+        if (interior)
+            block_levels<SEG, K, 1, true, true>(P, A, jlo, jhi, rn, rh, rows);
+        else
+            block_levels<SEG, K, 1, false, true>(P, A, jlo, jhi, rn, rh, rows);
+    } else if (interior) {
         block_levels<SEG, K, 1, true, false>(P, A, jlo, jhi, rn, rh, rows);
-    else
+    } else {
         block_levels<SEG, K, 1, false, false>(P, A, jlo, jhi, rn, rh, rows);
+    }
 }
 
 bool valid_block(int seg, int k) {
