@@ -154,7 +154,8 @@ def adjoint_ratio(args):
 
 
 def batched(args):
-    """The batched workload: persistent batched launch vs the plain stepper."""
+    """The batched workload: both batch modes (persistent graph launch, one
+    launch per iteration) at their best segment lengths vs the plain stepper."""
     import torch
     from paper_1001_3631_amd import workloads as W
     from paper_1001_3631_amd.engine import Batch, Engine
@@ -163,7 +164,10 @@ def batched(args):
     grids = [it["grid"] for it in inst]
     pts = sum(g["nr"] * g["nth"] for g in grids)
     b = Batch(grids)
-    tune = b.autotune(None)
+    tune = b.autotune(None)                         # [(seg_rows, mode, us)], fastest first
+    best_seg = {}
+    for seg, mode, _ in tune:
+        best_seg.setdefault(mode, seg)
     waves = [torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda") for g in grids]
 
     def evolve():
@@ -175,12 +179,20 @@ def batched(args):
         b.sync()
         return time.perf_counter() - t0
 
-    evolve()                                        # captures the graph for n iterations
-    tb = evolve()
-    for e in b.instances:
-        e.check_finite()
+    names = {Batch.PERSISTENT: "persistent", Batch.PER_ITERATION: "per_iteration"}
+    times = {}
+    for mode in (Batch.PERSISTENT, Batch.PER_ITERATION):
+        b.set_tuning(best_seg[mode])
+        b.set_mode(mode)
+        if mode == Batch.PERSISTENT:
+            evolve()                                # captures the graph for n iterations
+        times[mode] = evolve()
+        for e in b.instances:
+            e.check_finite()
     b.close()
     del waves
+    mode_b = min(times, key=times.get)
+    tb = times[mode_b]
 
     # plain stepper, one instance after another, same iterations and extraction
     tp = 0.0
@@ -196,8 +208,10 @@ def batched(args):
         tp += time.perf_counter() - t1
         eng.close()
     return {"workload": "batched_64_instances_seed3", "instances": len(grids), "points": pts,
-            "iterations": n, "seg_rows": tune[0][0],
+            "iterations": n, "mode": names[mode_b], "seg_rows": best_seg[mode_b],
             "batched_s": round(tb, 3), "batched_gpts": round(pts * n / tb / 1e9, 3),
+            "by_mode": {names[m]: {"seg_rows": best_seg[m], "s": round(times[m], 3),
+                                   "gpts": round(pts * n / times[m] / 1e9, 3)} for m in times},
             "plain_sequential_s": round(tp, 3), "plain_gpts": round(pts * n / tp / 1e9, 3),
             "batched_over_plain": round(tp / tb, 3)}
 

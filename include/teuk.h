@@ -252,23 +252,31 @@ int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
 typedef struct {
     int32_t seg_rows;
     int32_t k_steps;
+    int32_t batch_mode;     /* batches: TEUK_BATCH_*; 0 for a single context */
     double us_per_iteration;
 } teuk_tune_entry;
 
 int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
                   int32_t* count);
 
+#define TEUK_BATCH_PERSISTENT 0
+#define TEUK_BATCH_PER_ITERATION 1
+
 /* Batched stepping: many independent instances (each its own M, a, s, m,
- * grid and state) advanced together by ONE persistent kernel launch,
- * captured in a HIP graph together with a small kernel that resets its work
- * counters.  Work items are tiles (instance, strip of 62 r* columns over all
- * theta rows, walked in segments of seg_rows rows) of one iteration;
- * persistent waves take them from a global counter in iteration-major order,
- * and each item waits on per-tile completion counters of its neighbouring
- * strips (the iteration's data dependences, Sec. 3.2 half and full steps)
- * instead of a launch boundary.
+ * grid and state) advanced together, in one of two modes.
+ * TEUK_BATCH_PERSISTENT: ONE persistent kernel launch per call, captured in
+ *   a HIP graph together with a small kernel that resets its work counters.
+ *   Work items are tiles (instance, strip of 62 r* columns over all theta
+ *   rows, walked in segments of seg_rows rows) of one iteration; persistent
+ *   waves take them from a global counter in iteration-major order, and each
+ *   item waits on per-tile completion counters of its neighbouring strips
+ *   (the iteration's data dependences, Sec. 3.2 half and full steps) instead
+ *   of a launch boundary.
+ * TEUK_BATCH_PER_ITERATION: one launch per iteration covering every
+ *   instance, one wave per (instance, strip, theta segment); the launch
+ *   boundary orders the iterations.
  * Every point is evaluated by the same device code as teuk_step_n, so an
- * instance's results are bitwise equal to stepping it alone.
+ * instance's results are bitwise equal to stepping it alone, in both modes.
  *
  * teuk_batch_create: n >= 1 descriptors (host array); every instance gets a
  *   context as from teuk_init_grid on hip_stream (validation as there; the
@@ -278,20 +286,25 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  *   teuk_destroy refuses it (EINVAL), teuk_batch_destroy frees it.
  * teuk_batch_set_tuning / get_tuning: theta rows per segment, 4, 8 or 16
  *   (EINVAL otherwise); synchronizes.  The default is 16.
+ * teuk_batch_set_mode / get_mode: TEUK_BATCH_PERSISTENT (the default) or
+ *   TEUK_BATCH_PER_ITERATION (EINVAL otherwise); applies from the next
+ *   teuk_batch_step_n.
  * teuk_batch_step_n: nsteps (0 <= nsteps <= INT32_MAX) iterations of every
  *   instance.  waveforms = NULL or a host array of n device pointers, each
  *   NULL or nsteps * nth complex128 (the extraction column after every
  *   iteration, as teuk_step_n).  Instances must carry no source (EINVAL).
- *   Asynchronous; the graph for (nsteps, seg_rows) is captured on first use
- *   and cached.
- * teuk_batch_sync: synchronizes the stream and reports a launch that gave up
- *   (TEUK_EDEVICE): a dependency wait that exceeds 2 s of device wall clock
+ *   Asynchronous; in the persistent mode the graph for (nsteps, seg_rows) is
+ *   captured on first use and cached.
+ * teuk_batch_sync: synchronizes the stream and reports a persistent launch
+ *   that gave up (TEUK_EDEVICE): a dependency wait that exceeds 2 s of device
+ *   wall clock
  *   makes every wave of that launch, and of launches queued after it, exit
  *   early, leaving the states invalid.  Reading the report clears it.
- * teuk_batch_autotune: as teuk_autotune over seg_rows (k_steps is 1 for
- *   batches), timing 8 batched iterations per variant, all instance states
- *   saved and restored; cache key = architecture, the instance shapes and
- *   the kernel sources. */
+ * teuk_batch_autotune: as teuk_autotune over (batch_mode, seg_rows)
+ *   (k_steps is 1 for batches), timing 8 batched iterations per variant,
+ *   all instance states saved and restored; applies the fastest mode and
+ *   segment length.  Cache lines carry a fifth column, the mode; cache key
+ *   = architecture, the instance shapes and the kernel sources. */
 typedef struct teuk_batch teuk_batch;
 
 int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, teuk_batch** out);
@@ -299,6 +312,8 @@ int teuk_batch_destroy(teuk_batch* batch);
 int teuk_batch_instance(teuk_batch* batch, int32_t k, teuk_ctx** out);
 int teuk_batch_set_tuning(teuk_batch* batch, int32_t seg_rows);
 int teuk_batch_get_tuning(const teuk_batch* batch, int32_t* seg_rows);
+int teuk_batch_set_mode(teuk_batch* batch, int32_t mode);
+int teuk_batch_get_mode(const teuk_batch* batch, int32_t* mode);
 int teuk_batch_step_n(teuk_batch* batch, int64_t nsteps, void* const* waveforms);
 int teuk_batch_sync(teuk_batch* batch);
 int teuk_batch_autotune(teuk_batch* batch, const char* cache_path, teuk_tune_entry* table, int32_t capacity,

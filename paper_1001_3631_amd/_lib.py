@@ -49,8 +49,13 @@ class Tuning(ctypes.Structure):
 
 
 class TuneEntry(ctypes.Structure):
-    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32),
+    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
                 ("us_per_iteration", ctypes.c_double)]
+
+
+# teuk_batch modes
+BATCH_PERSISTENT = 0
+BATCH_PER_ITERATION = 1
 
 
 class SourceDesc(ctypes.Structure):
@@ -102,6 +107,8 @@ SIGNATURES = {
     "teuk_batch_instance": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(_CTX)]),
     "teuk_batch_set_tuning": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "teuk_batch_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
+    "teuk_batch_set_mode": (ctypes.c_int, [_CTX, ctypes.c_int32]),
+    "teuk_batch_get_mode": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
     "teuk_batch_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, ctypes.POINTER(_P)]),
     "teuk_batch_sync": (ctypes.c_int, [_CTX]),
     "teuk_batch_autotune": (ctypes.c_int, [_CTX, ctypes.c_char_p, ctypes.POINTER(TuneEntry), ctypes.c_int32,

@@ -1,5 +1,6 @@
 // C ABI of batched stepping: many independent instances advanced by one
-// persistent launch captured in a HIP graph (declared in include/teuk.h).
+// persistent launch captured in a HIP graph, or by one launch per iteration
+// that covers every instance (declared in include/teuk.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,7 +43,9 @@ struct teuk_batch {
     hipStream_t stream = nullptr;       // caller's stream: every launch and copy
     hipStream_t cap = nullptr;          // private stream used only to capture graphs
     int seg_rows = 8;
+    int mode = TEUK_BATCH_PERSISTENT;
     int ntiles = 0;                     // tiles per iteration at seg_rows
+    int items = 0;                      // (strip, segment) items per iteration at seg_rows
     int max_tiles = 0;                  // at the smallest segment (allocation size)
     int waves = 0;                      // persistent waves per launch
     int resident_waves = 0;             // 8 per CU (two per SIMD at the kernel's register use)
@@ -52,6 +55,7 @@ struct teuk_batch {
     int slot = 0;
     teuk::BatchInstance* d_inst = nullptr;
     int4* d_tiles = nullptr;
+    int* d_item0 = nullptr;             // per instance: first item (per-iteration mode), + total
     int* d_done = nullptr;
     unsigned long long* d_ticket = nullptr;
     int* d_abort = nullptr;
@@ -86,6 +90,7 @@ void free_batch(teuk_batch* b) {
     }
     (void)hipFree(b->d_inst);
     (void)hipFree(b->d_tiles);
+    (void)hipFree(b->d_item0);
     (void)hipFree(b->d_done);
     (void)hipFree(b->d_ticket);
     (void)hipFree(b->d_abort);
@@ -93,19 +98,34 @@ void free_batch(teuk_batch* b) {
     delete b;
 }
 
-// Tile list: instance-major, then strip; tile index = position in the list
-// (also the index of its done counter).  The segment length only changes
-// how each wave walks its strip.
+// Theta segments per strip at segment length seg (the last takes up to
+// seg + 2 rows, as in teuk_step_n).
+int segments(const teuk_ctx* c, int seg) { return (c->G.nth - 3) / seg + 1; }
+
+// Tile list of the persistent mode: instance-major, then strip; tile index =
+// position in the list (also the index of its done counter).  The segment
+// length only changes how each wave walks its strip.  Item offsets of the
+// per-iteration mode: instance k owns items [item0[k], item0[k+1]), one per
+// (strip, segment).
 int set_batch_tiles(teuk_batch* b, int seg) {
     std::vector<int4> tiles;
     tiles.reserve(b->max_tiles);
+    std::vector<int> item0;
+    long long items = 0;
     for (size_t k = 0; k < b->inst.size(); ++k) {
         teuk_ctx* c = b->inst[k];
         for (int s = 0; s < c->nstrips; ++s)
             tiles.push_back(make_int4(static_cast<int>(k), s, 0, static_cast<int>(tiles.size())));
+        item0.push_back(static_cast<int>(items));
+        items += static_cast<long long>(c->nstrips) * segments(c, seg);
+        if (items > INT_MAX - 3) return fail(TEUK_EINVAL, "too many work items in one batch");
     }
+    item0.push_back(static_cast<int>(items));
     HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice),
             "batch tiles");
+    HIP_TRY(hipMemcpy(b->d_item0, item0.data(), sizeof(int) * item0.size(), hipMemcpyHostToDevice),
+            "batch item offsets");
+    b->items = static_cast<int>(items);
     b->seg_rows = seg;
     b->ntiles = static_cast<int>(tiles.size());
     b->waves = std::max(1, std::min(b->resident_waves, b->ntiles));
@@ -135,7 +155,7 @@ int upload_instances(teuk_batch* b, void* const* waveforms) {
         I.ld = c->ld;
         I.rpitch = G.nr;
         I.nstrips = c->nstrips;
-        I.nseg = (G.nth - 3) / b->seg_rows + 1;
+        I.nseg = segments(c, b->seg_rows);
         I.dt = G.dt;
         I.inv_hr = 1.0 / G.h_r;
         I.ko_c = c->ko_c;
@@ -241,6 +261,7 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, 
     }
     if (e == hipSuccess) e = hipMalloc(&b->d_inst, sizeof(teuk::BatchInstance) * n);
     if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(int4) * b->max_tiles);
+    if (e == hipSuccess) e = hipMalloc(&b->d_item0, sizeof(int) * (static_cast<size_t>(n) + 1));
     if (e == hipSuccess) e = hipMalloc(&b->d_done, sizeof(int) * b->max_tiles);
     if (e == hipSuccess) e = hipMalloc(&b->d_ticket, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int));
@@ -289,6 +310,21 @@ int teuk_batch_get_tuning(const teuk_batch* b, int32_t* seg_rows) {
     return TEUK_OK;
 }
 
+int teuk_batch_set_mode(teuk_batch* b, int32_t mode) {
+    if (int rc = check_batch(b)) return rc;
+    if (mode != TEUK_BATCH_PERSISTENT && mode != TEUK_BATCH_PER_ITERATION)
+        return fail(TEUK_EINVAL, "mode must be TEUK_BATCH_PERSISTENT or TEUK_BATCH_PER_ITERATION");
+    b->mode = mode;
+    return TEUK_OK;
+}
+
+int teuk_batch_get_mode(const teuk_batch* b, int32_t* mode) {
+    if (int rc = check_batch(b)) return rc;
+    if (mode == nullptr) return fail(TEUK_EINVAL, "null output");
+    *mode = b->mode;
+    return TEUK_OK;
+}
+
 int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
     if (int rc = check_batch(b)) return rc;
     if (nsteps < 0 || nsteps > INT_MAX) return fail(TEUK_EINVAL, "nsteps out of range");
@@ -297,12 +333,21 @@ int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
         if (b->inst[k]->has_src)
             return fail(TEUK_EINVAL, "batched stepping evolves homogeneous instances; instance " +
                                          std::to_string(k) + " has a source");
-    if (static_cast<unsigned long long>(nsteps) * static_cast<unsigned long long>(b->ntiles) >= (1ull << 62))
-        return fail(TEUK_EINVAL, "too many work items in one launch");
-    hipGraphExec_t exec = nullptr;
-    if (int rc = graph_for(b, nsteps, &exec)) return rc;
-    if (int rc = upload_instances(b, waveforms)) return rc;
-    HIP_TRY(hipGraphLaunch(exec, b->stream), "batch graph launch");
+    if (b->mode == TEUK_BATCH_PER_ITERATION) {
+        if (int rc = upload_instances(b, waveforms)) return rc;
+        const int ninst = static_cast<int>(b->inst.size());
+        for (int64_t n = 0; n < nsteps; ++n)
+            HIP_TRY(teuk::launch_batch_iteration(b->d_inst, b->d_item0, ninst, b->items, static_cast<int>(n),
+                                                 b->seg_rows, b->stream),
+                    "batch iteration launch");
+    } else {
+        if (static_cast<unsigned long long>(nsteps) * static_cast<unsigned long long>(b->ntiles) >= (1ull << 62))
+            return fail(TEUK_EINVAL, "too many work items in one launch");
+        hipGraphExec_t exec = nullptr;
+        if (int rc = graph_for(b, nsteps, &exec)) return rc;
+        if (int rc = upload_instances(b, waveforms)) return rc;
+        HIP_TRY(hipGraphLaunch(exec, b->stream), "batch graph launch");
+    }
     for (teuk_ctx* c : b->inst) {
         c->cur ^= static_cast<int>(nsteps & 1);
         c->steps_done += nsteps;
@@ -366,27 +411,30 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
         teuk_tune_entry hit{};
         while (f && std::getline(f, line)) {
             std::istringstream ls(line);
-            std::string k, seg, kk, us;
+            std::string k, seg, kk, us, md;
             if (!std::getline(ls, k, '\t') || !std::getline(ls, seg, '\t') || !std::getline(ls, kk, '\t') ||
-                !std::getline(ls, us, '\t'))
+                !std::getline(ls, us, '\t') || !std::getline(ls, md, '\t'))
                 continue;
             if (k != key) continue;
             const int s = std::atoi(seg.c_str());
-            if (teuk::valid_segment_rows(s) && std::atoi(kk.c_str()) == 1) {
-                hit = {s, 1, std::atof(us.c_str())};
+            const int m = std::atoi(md.c_str());
+            if (teuk::valid_segment_rows(s) && std::atoi(kk.c_str()) == 1 &&
+                (m == TEUK_BATCH_PERSISTENT || m == TEUK_BATCH_PER_ITERATION)) {
+                hit = {s, 1, m, std::atof(us.c_str())};
                 found = true;
             }
         }
         if (found) {
             if (hit.seg_rows != b->seg_rows)
                 if (int rc = teuk_batch_set_tuning(b, hit.seg_rows)) return rc;
+            b->mode = hit.batch_mode;
             emit({hit});
             return TEUK_OK;
         }
     }
 
     // save every instance's current level, time each variant, restore
-    const int seg0 = b->seg_rows;
+    const int seg0 = b->seg_rows, mode0 = b->mode;
     std::vector<double2*> save;
     auto release = [&]() {
         for (double2* p : save) (void)hipFree(p);
@@ -434,11 +482,13 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
         return hip_fail(e, "batch autotune events");
     }
     std::vector<teuk_tune_entry> cand;
-    for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, 0.0});
+    for (int mode : {TEUK_BATCH_PERSISTENT, TEUK_BATCH_PER_ITERATION})
+        for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, mode, 0.0});
     constexpr int kRounds = 8, kReps = 3;
     int rc = TEUK_OK;
     for (auto& t : cand) {
         rc = teuk_batch_set_tuning(b, t.seg_rows);
+        if (rc == TEUK_OK) rc = teuk_batch_set_mode(b, t.batch_mode);
         if (rc == TEUK_OK) rc = teuk_batch_step_n(b, kRounds, nullptr);   // warm-up (and capture)
         double best = 1e300;
         for (int r = 0; rc == TEUK_OK && r < kReps; ++r) {
@@ -460,18 +510,20 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
     for (auto& x : ev) (void)hipEventDestroy(x);
     if (rc != TEUK_OK) {
         (void)teuk_batch_set_tuning(b, seg0);
+        b->mode = mode0;
         return fail(rc, msg);
     }
     std::stable_sort(cand.begin(), cand.end(), [](const teuk_tune_entry& x, const teuk_tune_entry& y) {
         return x.us_per_iteration < y.us_per_iteration;
     });
     if (int r2 = teuk_batch_set_tuning(b, cand[0].seg_rows)) return r2;
+    b->mode = cand[0].batch_mode;
     emit(cand);
     if (cache_path != nullptr) {
         std::ofstream f(cache_path, std::ios::app);
         char line[512];
-        std::snprintf(line, sizeof(line), "%s\t%d\t%d\t%.4f\n", key.c_str(), cand[0].seg_rows, 1,
-                      cand[0].us_per_iteration);
+        std::snprintf(line, sizeof(line), "%s\t%d\t%d\t%.4f\t%d\n", key.c_str(), cand[0].seg_rows, 1,
+                      cand[0].us_per_iteration, cand[0].batch_mode);
         if (!(f << line)) return fail(TEUK_EINVAL, std::string("cannot append to tuning cache ") + cache_path);
     }
     return TEUK_OK;

@@ -1,4 +1,5 @@
-// Batched persistent stepping of many independent instances.
+// Batched stepping of many independent instances: the persistent kernel and
+// the one-launch-per-iteration kernel.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -103,16 +104,18 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
         // the instance's fields are the same in every lane: keep them in
-        // scalar registers (the vector registers go to the stencil)
+        // scalar registers (the vector registers go to the stencil); the
+        // pointers are rebuilt as global (planes, radial records) and constant
+        // (angular records, never written) pointers
         StepParams P;
         const int lv = uni(I.cur + n) & 1;
-        P.phi = uni(I.plane[lv][0]);
-        P.pi = uni(I.plane[lv][1]);
-        P.phi_out = uni(I.plane[lv ^ 1][0]);
-        P.pi_out = uni(I.plane[lv ^ 1][1]);
-        P.rnode = uni(I.rnode);
-        P.rhalf = uni(I.rhalf);
-        P.rows = uni(I.rows);
+        P.phi = global_ptr(uni(I.plane[lv][0]));
+        P.pi = global_ptr(uni(I.plane[lv][1]));
+        P.phi_out = global_ptr(uni(I.plane[lv ^ 1][0]));
+        P.pi_out = global_ptr(uni(I.plane[lv ^ 1][1]));
+        P.rnode = global_ptr(uni(I.rnode));
+        P.rhalf = global_ptr(uni(I.rhalf));
+        P.rows = constant_ptr(uni(I.rows));
         P.nr = uni(I.nr);
         P.nth = uni(I.nth);
         P.ld = uni(I.ld);
@@ -129,7 +132,7 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         P.fh = P.fn = nullptr;
         P.org = nullptr;
         P.win_r = P.win_t = 0;
-        double2* const wave = uni(I.wave);
+        double2* const wave = global_ptr(uni(I.wave));
         LevelArgs A;
         A.lane = lane;
         A.i = strip * 62 - 1 + lane;
@@ -171,6 +174,93 @@ __global__ void __launch_bounds__(256) batch_reset_kernel(BatchParams B) {
 
 hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((B.ntiles + 255) / 256), dim3(256), 0, stream, B);
+    return hipGetLastError();
+}
+
+// One iteration of every instance of a batch in one launch (the batch's
+// per-iteration mode): the launch boundary orders the iterations, so there
+// are no dependency counters or fences.  Work item = one wave on (instance,
+// strip of 62 columns, theta segment), numbered instance-major: the items of
+// instance k are [item0[k], item0[k+1]), strip-major as in lw_step_kernel.
+// Four waves per workgroup; the instance table and item0 are read-only for
+// the launch, so the wave-uniform reads go through the scalar cache.
+template <int SEG>
+__global__ void __launch_bounds__(256) lw_multi_kernel(const BatchInstance* __restrict__ inst,
+                                                       const int* __restrict__ item0, int ninst, int n) {
+    const int lane = threadIdx.x & 63;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+    if (item >= item0[ninst]) return;   // uniform per wave
+    // instance: the last k with item0[k] <= item (item0 is non-decreasing)
+    int k0 = 0, k1 = ninst - 1;
+    while (k0 < k1) {
+        const int mid = (k0 + k1 + 1) >> 1;
+        if (item0[mid] <= item) k0 = mid;
+        else k1 = mid - 1;
+    }
+    const BatchInstance& I = inst[k0];
+    const int local = item - item0[k0];
+    const int strip = local / I.nseg;
+    const int seg = local - strip * I.nseg;
+
+    StepParams P;
+    const int lv = (I.cur + n) & 1;
+    P.phi = global_ptr(I.plane[lv][0]);
+    P.pi = global_ptr(I.plane[lv][1]);
+    P.phi_out = global_ptr(I.plane[lv ^ 1][0]);
+    P.pi_out = global_ptr(I.plane[lv ^ 1][1]);
+    P.rnode = global_ptr(I.rnode);
+    P.rhalf = global_ptr(I.rhalf);
+    P.rows = constant_ptr(I.rows);
+    P.nr = I.nr;
+    P.nth = I.nth;
+    P.ld = I.ld;
+    P.rpitch = I.rpitch;
+    P.nstrips = I.nstrips;
+    P.nseg = I.nseg;
+    P.dt = I.dt;
+    P.inv_hr = I.inv_hr;
+    P.ko_c = I.ko_c;
+    P.even = I.even;
+    P.kerr = I.kerr;
+    P.i_ext = I.i_ext;
+    P.wave = nullptr;
+    P.fh = P.fn = nullptr;
+    P.org = nullptr;
+    P.win_r = P.win_t = 0;
+    LevelArgs A;
+    A.lane = lane;
+    A.i = strip * 62 - 1 + lane;
+    A.halo = 1;
+    A.fh = A.fn = nullptr;
+    A.org = make_int4(0, 0, 0, 0);
+    A.wave = I.wave ? global_ptr(I.wave) + static_cast<size_t>(n) * P.nth : nullptr;
+    A.lp = A.lq = nullptr;
+    A.lbase = 0;
+    A.lo = seg * SEG;
+    A.hi = (seg == P.nseg - 1) ? P.nth : A.lo + SEG;
+    const int ic = min(max(A.i, 0), P.nr - 1);
+    const int ih = min(max(A.i, 0), P.nr - 2);
+    const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
+    const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
+    const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 && A.lo >= 4 &&
+                          A.hi <= P.nth - 2;
+    if (interior)   // uniform per wave
+        stream_level<SEG + 2, false, false, kPrefetchRows, SEG>(P, A, rn, rh, P.rows);
+    else
+        stream_level<SEG + 2, false, false, kPrefetchRows>(P, A, rn, rh, P.rows);
+}
+
+hipError_t launch_batch_iteration(const BatchInstance* inst, const int* item0, int ninst, int items, int n,
+                                  int seg, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    const dim3 grid((items + 3) / 4), block(256);
+    switch (seg) {
+        case 4: hipLaunchKernelGGL(lw_multi_kernel<4>, grid, block, 0, stream, inst, item0, ninst, n); break;
+        case 8: hipLaunchKernelGGL(lw_multi_kernel<8>, grid, block, 0, stream, inst, item0, ninst, n); break;
+        case 16: hipLaunchKernelGGL(lw_multi_kernel<16>, grid, block, 0, stream, inst, item0, ninst, n); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -827,8 +827,8 @@ int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, i
     }
 
     std::vector<teuk_tune_entry> cand;
-    for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, 0.0});
-    for (const auto& v : teuk::kBlockVariants) cand.push_back({v.seg, v.k, 0.0});
+    for (int seg : teuk::kSegVariants) cand.push_back({seg, 1, 0, 0.0});
+    for (const auto& v : teuk::kBlockVariants) cand.push_back({v.seg, v.k, 0, 0.0});
 
     // save what the trials disturb
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;

@@ -37,6 +37,37 @@ __device__ __forceinline__ double2 from_prev(double2 v) {
     return make_double2(dpp_move<0x138>(v.x), dpp_move<0x138>(v.y));   // wave_shr:1
 }
 
+// A pointer that reaches a kernel through memory (an instance table) rather
+// than as an argument is generic to the compiler: loads and stores through it
+// become flat instructions, which also count against the scalar-memory
+// counter, so each wait for an angular record (a scalar load) would also wait
+// for every row in flight.  Rebuilding the pointer in the global address
+// space (device pass only; the address is the same) makes them global
+// instructions.
+template <typename T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)(G)(reinterpret_cast<unsigned long long>(p));
+#else
+    return p;
+#endif
+}
+
+// The same for a table that nothing writes while the kernel runs (the
+// angular records), rebuilt in the constant address space: its wave-uniform
+// reads become scalar loads even after the kernel's own stores, which the
+// compiler cannot otherwise rule out as aliasing it.
+template <typename T>
+__device__ __forceinline__ const T* constant_ptr(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using C = __attribute__((address_space(4))) const T*;
+    return (const T*)(C)(reinterpret_cast<unsigned long long>(p));
+#else
+    return p;
+#endif
+}
+
 // Source value at (col, row) of a window table with origin (c0, r0), zero
 // outside it.
 __device__ __forceinline__ double2 window_value(const double2* __restrict__ tab, int c0, int r0, int win_r,

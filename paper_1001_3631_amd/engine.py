@@ -259,10 +259,15 @@ class Engine:
 
 
 class Batch:
-    """Many independent instances stepped by one persistent launch (teuk_batch_*).
+    """Many independent instances stepped together (teuk_batch_*): one
+    persistent graph launch per call, or one launch per iteration covering
+    every instance (mode, see set_mode).
 
     grids: list of dicts with Engine's grid parameters.  instances[k] is an
     Engine view of instance k (set_state, init_pulse, get_state, ...)."""
+
+    PERSISTENT = L.BATCH_PERSISTENT
+    PER_ITERATION = L.BATCH_PER_ITERATION
 
     def __init__(self, grids, stream=None):
         self._lib = L.load()
@@ -306,6 +311,16 @@ class Batch:
     def set_tuning(self, seg_rows):
         L.check(self._lib.teuk_batch_set_tuning(self.ctx, int(seg_rows)))
 
+    @property
+    def mode(self):
+        v = ctypes.c_int32()
+        L.check(self._lib.teuk_batch_get_mode(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_mode(self, mode):
+        """Batch.PERSISTENT or Batch.PER_ITERATION."""
+        L.check(self._lib.teuk_batch_set_mode(self.ctx, int(mode)))
+
     def step(self, nsteps, waveform=True, out=None):
         """nsteps iterations of every instance; returns the per-instance
         (nsteps, nth) waveforms (out, if given), or None."""
@@ -327,9 +342,12 @@ class Batch:
         L.check(self._lib.teuk_batch_sync(self.ctx))
 
     def autotune(self, cache_path=None):
-        cap = 8
+        """Measure every (mode, seg_rows) (or take it from the cache file) and
+        keep the fastest; returns [(seg_rows, mode, us/iteration)], fastest
+        first (one entry when served from the cache)."""
+        cap = 16
         table = (L.TuneEntry * cap)()
         cnt = ctypes.c_int32()
         path = None if cache_path is None else os.fsencode(cache_path)
         L.check(self._lib.teuk_batch_autotune(self.ctx, path, table, cap, ctypes.byref(cnt)))
-        return [(table[k].seg_rows, table[k].k_steps, table[k].us_per_iteration) for k in range(cnt.value)]
+        return [(table[k].seg_rows, table[k].batch_mode, table[k].us_per_iteration) for k in range(cnt.value)]

@@ -1,10 +1,11 @@
-"""Batched persistent stepping through the C ABI.
+"""Batched stepping through the C ABI, in both modes (one persistent graph
+launch per call; one launch per iteration covering every instance).
 
 Each instance of a batch must end bitwise equal to the same instance stepped
 alone with teuk_step_n (same per-point device code): states and waveform rows,
 for heterogeneous instances (a, m, s, grid shapes down to nr = 5, nth = 7,
 dissipation on and off), for repeated launches of a cached graph, for a new
-iteration count (new graph), and for every segment length.  One instance is
+iteration count (new graph), for every segment length and both modes.  One instance is
 also checked against the oracle directly, and the batched workload's real
 shapes are covered by a subset of its instances.
 """
@@ -47,10 +48,13 @@ def single_runs(grids, states, plan):
     return out
 
 
-def batch_runs(grids, states, plan, seg=None):
+def batch_runs(grids, states, plan, seg=None, mode=None):
     b = make_batch(grids)
     if seg is not None:
         b.set_tuning(seg)
+    if mode is not None:
+        b.set_mode(mode)
+        assert b.mode == mode
     for e, (phi, pi) in zip(b.instances, states):
         e.set_state(to_dev(phi), to_dev(pi))
     ws = [[] for _ in grids]
@@ -79,20 +83,25 @@ MIXED = STEP_GRIDS + [
 ]
 
 
+MODES = [0, 1]   # Batch.PERSISTENT, Batch.PER_ITERATION
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
 @pytest.mark.parametrize("seg", [4, 8, 16])
-def test_batch_bitwise_equal_to_single_instances(seg):
+def test_batch_bitwise_equal_to_single_instances(seg, mode):
     states = [W.random_state(g["nth"], g["nr"], seed=31 + k) for k, g in enumerate(MIXED)]
     plan = [5, 5, 3]            # a cached graph replayed, then a new iteration count
     ref = single_runs(MIXED, states, plan)
-    got = batch_runs(MIXED, states, plan, seg=seg)
+    got = batch_runs(MIXED, states, plan, seg=seg, mode=mode)
     for a, b in zip(got, ref):
         assert_bitwise(a, b)
 
 
-def test_batch_instance_against_oracle():
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_batch_instance_against_oracle(mode):
     grids = MIXED[:3]
     states = [W.random_state(g["nth"], g["nr"], seed=41 + k) for k, g in enumerate(grids)]
-    got = batch_runs(grids, states, [4])
+    got = batch_runs(grids, states, [4], mode=mode)
     for g_d, (phi, pi), (w, p, q) in zip(grids, states, got):
         g = T.Grid(**g_d)
         rp, rq = phi, pi
@@ -105,7 +114,8 @@ def test_batch_instance_against_oracle():
         assert rel(w, np.array(rw)) <= 1e-13
 
 
-def test_batched_workload_subset_bitwise():
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_batched_workload_subset_bitwise(mode):
     """Instances of the batched workload at their real sizes (one of each grid
     level), Gaussian pulses, 12 iterations."""
     inst = W.batched_instances()
@@ -117,6 +127,7 @@ def test_batched_workload_subset_bitwise():
                 break
     grids = [it["grid"] for it in pick]
     b = make_batch(grids)
+    b.set_mode(mode)
     for e, it in zip(b.instances, pick):
         e.init_pulse(**it["pulse"])
     ws = b.step(12)
@@ -139,6 +150,9 @@ def test_batch_rejects_sources_and_bad_arguments():
     b = make_batch(grids)
     with pytest.raises(TeukError):
         b.set_tuning(12)
+    with pytest.raises(TeukError):
+        b.set_mode(2)
+    assert b.mode == 0
     e = b.instances[0]
     orbit = e.orbit_circular(10.0, 9, M=1.0, a=grids[0]["a"])
     e.set_source(orbit, 1.0, 2.0, 2.0, 8.0)
@@ -157,11 +171,14 @@ def test_batch_autotune_restores_states(tmp_path):
     b.step(3, waveform=False)
     before = [tuple(host(x) for x in e.get_state()) for e in b.instances]
     table = b.autotune(str(tmp_path / "tune.txt"))
-    assert {s for s, _, _ in table} == {4, 8, 16}
-    assert b.seg_rows == table[0][0]
+    assert {(s, m) for s, m, _ in table} == {(s, m) for s in (4, 8, 16) for m in MODES}
+    assert (b.seg_rows, b.mode) == table[0][:2]
     for e, st in zip(b.instances, before):
         assert_bitwise(tuple(host(x) for x in e.get_state()), st)
         assert e.info["steps_done"] == 3
+    b.set_tuning(4 if table[0][0] != 4 else 8)
+    b.set_mode(1 - table[0][1])
     hit = b.autotune(str(tmp_path / "tune.txt"))
-    assert len(hit) == 1 and hit[0][0] == table[0][0]
+    assert len(hit) == 1 and hit[0][:2] == table[0][:2]
+    assert (b.seg_rows, b.mode) == table[0][:2]
     b.close()
