@@ -15,9 +15,13 @@ Also reported on the same JSON line:
   hbm_grid      the same physics on 12800 x 256 (larger than the last-level
                 cache), GPts/s and algorithmic GB/s;
   batched       64 independent instances of uneven size (seeded m, a, grid
-                level, pulse centre), 10000 iterations each, in one persistent
-                launch per evolution captured in a HIP graph, against the
-                plain stepper running the same instances one after another;
+                level, pulse centre), 10000 iterations each, in both batch
+                modes (one persistent launch per evolution captured in a HIP
+                graph; one launch per iteration over all instances), against
+                the plain stepper running the same instances one after another;
+  all_m         every m (1..4) of one circular orbit on the 6400 x 128 grid,
+                each with its source, 4000 iterations as one batch, against
+                the same instances one after another;
   cpu_baseline  the FP64 oracle on the host for a bounded number of
                 iterations of the same workload.
 """
@@ -61,7 +65,9 @@ def parse():
     ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance workloads")
+    ap.add_argument("--all-m-iterations", type=int, default=None,
+                    help="iterations of the all-m batch (default: the workload's 4000)")
     ap.add_argument("--batched-iterations", type=int, default=10000)
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
@@ -216,6 +222,65 @@ def batched(args):
             "batched_over_plain": round(tp / tb, 3)}
 
 
+def all_m(args):
+    """Every m of one orbit (m = 1..4, each with the orbit's source) as one
+    batch against the same instances stepped one after another."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    from paper_1001_3631_amd.engine import Batch, Engine
+    cfg = W.ALL_M
+    grids, src = cfg["grids"], cfg["source"]
+    n = args.all_m_iterations or cfg["steps"]
+    pts = sum(g["nr"] * g["nth"] for g in grids)
+
+    def attach(e, g):
+        orbit = e.orbit_circular(src["r0"], 2 * n + 1, M=g["M"], a=g["a"])
+        e.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+
+    b = Batch(grids)
+    for e, g in zip(b.instances, grids):
+        attach(e, g)
+    tune = b.autotune(None)                         # sources detached while timing
+    waves = [torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda") for g in grids]
+    z = [torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda") for g in grids]
+
+    def evolve():
+        for e, zz in zip(b.instances, z):
+            e.set_state(zz, zz)                     # zero data, source clock back to 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(n, out=waves)
+        b.sync()
+        return time.perf_counter() - t0
+
+    evolve()
+    tb = evolve()
+    for e in b.instances:
+        e.check_finite()
+    b.close()
+    del waves
+
+    tp = 0.0
+    for g in grids:
+        eng = Engine(**g)
+        eng.autotune(None)
+        attach(eng, g)
+        w = torch.empty((n, g["nth"]), dtype=torch.complex128, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        eng.step(n, out=w)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t1
+        eng.check_finite()
+        eng.close()
+    names = {Batch.PERSISTENT: "persistent", Batch.PER_ITERATION: "per_iteration"}
+    return {"workload": cfg["name"], "instances": len(grids), "points": pts, "iterations": n,
+            "mode": names[tune[0][1]], "seg_rows": tune[0][0],
+            "batched_s": round(tb, 3), "batched_gpts": round(pts * n / tb / 1e9, 3),
+            "plain_sequential_s": round(tp, 3), "plain_gpts": round(pts * n / tp / 1e9, 3),
+            "batched_over_plain": round(tp / tb, 3)}
+
+
 def cpu_baseline(cfg, iters):
     import numpy as np
     from oracle import teuk_oracle as T
@@ -327,6 +392,8 @@ def main():
     if not args.no_batched:
         extra["batched"] = batched(args)
         print(f"[bench] batched: {extra['batched']}", file=sys.stderr, flush=True)
+        extra["all_m"] = all_m(args)
+        print(f"[bench] all_m: {extra['all_m']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

@@ -292,17 +292,23 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  * teuk_batch_step_n: nsteps (0 <= nsteps <= INT32_MAX) iterations of every
  *   instance.  waveforms = NULL or a host array of n device pointers, each
  *   NULL or nsteps * nth complex128 (the extraction column after every
- *   iteration, as teuk_step_n).  Instances must carry no source (EINVAL).
- *   Asynchronous; in the persistent mode the graph for (nsteps, seg_rows) is
- *   captured on first use and cached.
+ *   iteration, as teuk_step_n).  Instances may carry sources (teuk_set_source
+ *   on the instance: e.g. every m of one orbit, or an inspiralling orbit
+ *   table); then the iterations go in chunks of at most 256, each preceded by
+ *   the compact source pass of every instance that has one, exactly as
+ *   teuk_step_n would run it.  ESTATE if an instance's orbit has too few
+ *   samples for nsteps more iterations (nothing is launched).  Asynchronous;
+ *   in the persistent mode the graph for (rounds, seg_rows) is captured on
+ *   first use and cached.
  * teuk_batch_sync: synchronizes the stream and reports a persistent launch
  *   that gave up (TEUK_EDEVICE): a dependency wait that exceeds 2 s of device
  *   wall clock
  *   makes every wave of that launch, and of launches queued after it, exit
  *   early, leaving the states invalid.  Reading the report clears it.
  * teuk_batch_autotune: as teuk_autotune over (batch_mode, seg_rows)
- *   (k_steps is 1 for batches), timing 8 batched iterations per variant,
- *   all instance states saved and restored; applies the fastest mode and
+ *   (k_steps is 1 for batches), timing 8 batched iterations per variant with
+ *   sources detached, all instance states, clocks and sources restored
+ *   afterwards; applies the fastest mode and
  *   segment length.  Cache lines carry a fifth column, the mode; cache key
  *   = architecture, the instance shapes and the kernel sources. */
 typedef struct teuk_batch teuk_batch;

@@ -23,6 +23,7 @@
 
 using teuk_detail::fail;
 using teuk_detail::hip_fail;
+using teuk_detail::kSourceBatch;
 
 namespace {
 
@@ -132,10 +133,20 @@ int set_batch_tiles(teuk_batch* b, int seg) {
     return TEUK_OK;
 }
 
+// Source windows of a launch's first iteration in an instance's tables (all
+// null without a source).
+struct SourceView {
+    const double2* fh = nullptr;
+    const double2* fn = nullptr;
+    const int4* org = nullptr;
+    int win_r = 0, win_t = 0;
+};
+
 // Instance table of the next launch: static fields plus each instance's
-// current level and waveform pointer.  Alternates between two pinned
-// buffers; a buffer is rewritten only after its previous copy has finished.
-int upload_instances(teuk_batch* b, void* const* waveforms) {
+// current level, waveform pointer (row offset `row` of its buffer) and
+// source windows.  Alternates between two pinned buffers; a buffer is
+// rewritten only after its previous copy has finished.
+int upload_instances(teuk_batch* b, void* const* waveforms, int64_t row, const std::vector<SourceView>& src) {
     const int k = b->slot;
     b->slot ^= 1;
     HIP_TRY(hipEventSynchronize(b->h_inst_free[k]), "batch table reuse");
@@ -164,7 +175,12 @@ int upload_instances(teuk_batch* b, void* const* waveforms) {
         I.i_ext = G.i_ext;
         I.cur = c->cur;
         I.tile0 = tile0;
-        I.wave = waveforms ? static_cast<double2*>(waveforms[j]) : nullptr;
+        I.wave = (waveforms && waveforms[j]) ? static_cast<double2*>(waveforms[j]) + row * G.nth : nullptr;
+        I.fh = src[j].fh;
+        I.fn = src[j].fn;
+        I.org = src[j].org;
+        I.win_r = src[j].win_r;
+        I.win_t = src[j].win_t;
         tile0 += I.nstrips;
     }
     HIP_TRY(hipMemcpyAsync(b->d_inst, h, sizeof(teuk::BatchInstance) * b->inst.size(), hipMemcpyHostToDevice,
@@ -329,28 +345,61 @@ int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
     if (int rc = check_batch(b)) return rc;
     if (nsteps < 0 || nsteps > INT_MAX) return fail(TEUK_EINVAL, "nsteps out of range");
     if (nsteps == 0) return TEUK_OK;
-    for (size_t k = 0; k < b->inst.size(); ++k)
-        if (b->inst[k]->has_src)
-            return fail(TEUK_EINVAL, "batched stepping evolves homogeneous instances; instance " +
-                                         std::to_string(k) + " has a source");
-    if (b->mode == TEUK_BATCH_PER_ITERATION) {
-        if (int rc = upload_instances(b, waveforms)) return rc;
-        const int ninst = static_cast<int>(b->inst.size());
-        for (int64_t n = 0; n < nsteps; ++n)
-            HIP_TRY(teuk::launch_batch_iteration(b->d_inst, b->d_item0, ninst, b->items, static_cast<int>(n),
-                                                 b->seg_rows, b->stream),
-                    "batch iteration launch");
-    } else {
-        if (static_cast<unsigned long long>(nsteps) * static_cast<unsigned long long>(b->ntiles) >= (1ull << 62))
-            return fail(TEUK_EINVAL, "too many work items in one launch");
-        hipGraphExec_t exec = nullptr;
-        if (int rc = graph_for(b, nsteps, &exec)) return rc;
-        if (int rc = upload_instances(b, waveforms)) return rc;
-        HIP_TRY(hipGraphLaunch(exec, b->stream), "batch graph launch");
+    bool any_src = false;
+    for (size_t k = 0; k < b->inst.size(); ++k) {
+        const teuk_ctx* c = b->inst[k];
+        if (!c->has_src) continue;
+        any_src = true;
+        if (2 * (c->steps_done + nsteps - 1) + 1 >= c->nsamples)
+            return fail(TEUK_ESTATE, "instance " + std::to_string(k) + ": orbit has too few samples for the "
+                                                                     "requested steps");
     }
-    for (teuk_ctx* c : b->inst) {
-        c->cur ^= static_cast<int>(nsteps & 1);
-        c->steps_done += nsteps;
+    // With sources the iterations go in chunks of at most one source batch:
+    // each chunk starts with the compact source pass of every instance that
+    // has a source (as teuk_step_n), then the chunk's launch(es).
+    const int64_t chunk_max = any_src ? kSourceBatch : nsteps;
+    if (static_cast<unsigned long long>(chunk_max) * static_cast<unsigned long long>(b->ntiles) >= (1ull << 62))
+        return fail(TEUK_EINVAL, "too many work items in one launch");
+    std::vector<SourceView> src(b->inst.size());
+    for (int64_t done = 0; done < nsteps;) {
+        const int64_t len = std::min(nsteps - done, chunk_max);
+        for (size_t k = 0; k < b->inst.size(); ++k) {
+            teuk_ctx* c = b->inst[k];
+            if (!c->has_src) continue;
+            const int64_t n = c->steps_done;
+            const int64_t span = (c->nsamples - 2) / 2 - n + 1;   // iterations the orbit still supports
+            size_t slot = 0;
+            if (int rc = teuk_detail::ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
+            if (static_cast<int64_t>(slot) + len > c->batch_len) {   // the chunk must fit one batch
+                c->batch_n0 = -1;                                     // (empty: start a new one at n)
+                c->batch_len = 0;
+                if (int rc = teuk_detail::ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
+            }
+            const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;
+            src[k].fh = c->d_fh + slot * wsz;
+            src[k].fn = c->d_fn + slot * wsz;
+            src[k].org = c->d_org + slot;
+            src[k].win_r = c->win_r;
+            src[k].win_t = c->win_t;
+        }
+        if (b->mode == TEUK_BATCH_PER_ITERATION) {
+            if (int rc = upload_instances(b, waveforms, done, src)) return rc;
+            const int ninst = static_cast<int>(b->inst.size());
+            for (int64_t n = 0; n < len; ++n)
+                HIP_TRY(teuk::launch_batch_iteration(b->d_inst, b->d_item0, ninst, b->items, static_cast<int>(n),
+                                                     b->seg_rows, b->stream),
+                        "batch iteration launch");
+        } else {
+            hipGraphExec_t exec = nullptr;
+            if (int rc = graph_for(b, len, &exec)) return rc;
+            if (int rc = upload_instances(b, waveforms, done, src)) return rc;
+            HIP_TRY(hipGraphLaunch(exec, b->stream), "batch graph launch");
+        }
+        for (teuk_ctx* c : b->inst) {
+            c->cur ^= static_cast<int>(len & 1);
+            c->steps_done += len;
+        }
+        done += len;
     }
     return TEUK_OK;
 }
@@ -454,11 +503,16 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
                     "batch autotune save");
         }
     }
+    // sources are detached while timing (the compact source pass is a small
+    // part of an iteration, and the orbits need not extend past the call)
     std::vector<int> cur0;
     std::vector<int64_t> steps_done0;
+    std::vector<char> src0;
     for (teuk_ctx* c : b->inst) {
         cur0.push_back(c->cur);
         steps_done0.push_back(c->steps_done);
+        src0.push_back(c->has_src ? 1 : 0);
+        c->has_src = false;
     }
     auto restore = [&]() {
         (void)hipStreamSynchronize(b->stream);
@@ -467,6 +521,7 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
             const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
             c->cur = cur0[k];
             c->steps_done = steps_done0[k];
+            c->has_src = src0[k] != 0;
             for (int f = 0; f < 2; ++f)
                 (void)hipMemcpyAsync(c->plane[c->cur][f], save[2 * k + f], bytes, hipMemcpyDeviceToDevice,
                                      b->stream);

@@ -32,6 +32,24 @@ __device__ __forceinline__ T* uni(T* p) {
     return reinterpret_cast<T*>((hi << 32) | lo);
 }
 
+// Source windows of iteration n of the launch (an instance's fh, fn, org,
+// win_r, win_t; see BatchInstance) into P and A, and whether they meet the
+// wave's columns [i0, i0 + 63] around the rows [A.lo, A.hi).
+__device__ __forceinline__ void batch_source(const double2* fh, const double2* fn, const int4* org, int win_r,
+                                             int win_t, int n, StepParams& P, LevelArgs& A) {
+    if (fh == nullptr || fn == nullptr || org == nullptr || win_r <= 0 || win_t <= 0) return;
+    const size_t wsz = static_cast<size_t>(win_r) * win_t;
+    P.win_r = win_r;
+    P.win_t = win_t;
+    A.fh = global_ptr(fh + static_cast<size_t>(n) * wsz);
+    A.fn = global_ptr(fn + static_cast<size_t>(n) * wsz);
+    A.org = constant_ptr(org)[n];
+}
+__device__ __forceinline__ bool source_meets(const StepParams& P, const LevelArgs& A, int i0) {
+    return A.fh != nullptr && (window_meets(A.org, false, P.win_r, P.win_t, i0, A.lo - 1, A.hi) ||
+                               window_meets(A.org, true, P.win_r, P.win_t, i0, A.lo, A.hi - 1));
+}
+
 }  // namespace
 
 // Batched persistent stepping: many independent instances (each its own
@@ -142,17 +160,21 @@ __global__ void __launch_bounds__(64) lw_batch_kernel(BatchParams B) {
         A.wave = wave ? wave + static_cast<size_t>(n) * P.nth : nullptr;
         A.lp = A.lq = nullptr;
         A.lbase = 0;
+        batch_source(uni(I.fh), uni(I.fn), uni(I.org), uni(I.win_r), uni(I.win_t), n, P, A);
         const int ic = min(max(A.i, 0), P.nr - 1);
         const int ih = min(max(A.i, 0), P.nr - 2);
         const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
         const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
         // segments away from the poles on a strip of interior columns take
-        // the interior form of the level (the same arithmetic)
+        // the interior form of the level, segments a source window meets the
+        // form with lookups (the same arithmetic)
         const bool cols_interior = strip >= 1 && strip * 62 + 64 <= P.nr;
         for (int q = 0; q < P.nseg; ++q) {
             A.lo = q * SEG;
             A.hi = (q == P.nseg - 1) ? P.nth : A.lo + SEG;
-            if (cols_interior && q != P.nseg - 1 && A.lo >= 4 && A.hi <= P.nth - 2)
+            if (source_meets(P, A, strip * 62 - 1))
+                stream_level<SEG + 2, false, false, kBatchPrefetchRows, 0, true>(P, A, rn, rh, P.rows);
+            else if (cols_interior && q != P.nseg - 1 && A.lo >= 4 && A.hi <= P.nth - 2)
                 stream_level<SEG + 2, false, false, kBatchPrefetchRows, SEG>(P, A, rn, rh, P.rows);
             else
                 stream_level<SEG + 2, false, false, kBatchPrefetchRows>(P, A, rn, rh, P.rows);
@@ -239,13 +261,16 @@ __global__ void __launch_bounds__(256) lw_multi_kernel(const BatchInstance* __re
     A.lbase = 0;
     A.lo = seg * SEG;
     A.hi = (seg == P.nseg - 1) ? P.nth : A.lo + SEG;
+    batch_source(I.fh, I.fn, I.org, I.win_r, I.win_t, n, P, A);
     const int ic = min(max(A.i, 0), P.nr - 1);
     const int ih = min(max(A.i, 0), P.nr - 2);
     const RCol rn = load_rcol(P.rnode, P.rpitch, ic);
     const RCol rh = load_rcol(P.rhalf, P.rpitch, ih);
     const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 && A.lo >= 4 &&
                           A.hi <= P.nth - 2;
-    if (interior)   // uniform per wave
+    if (source_meets(P, A, strip * 62 - 1))   // uniform per wave
+        stream_level<SEG + 2, false, false, kPrefetchRows, 0, true>(P, A, rn, rh, P.rows);
+    else if (interior)
         stream_level<SEG + 2, false, false, kPrefetchRows, SEG>(P, A, rn, rh, P.rows);
     else
         stream_level<SEG + 2, false, false, kPrefetchRows>(P, A, rn, rh, P.rows);

@@ -34,9 +34,11 @@ int hip_fail(hipError_t e, const char* what) {
 
 }  // namespace teuk_detail
 
+using teuk_detail::ensure_source;
 using teuk_detail::fail;
 using teuk_detail::g_last_error;
 using teuk_detail::hip_fail;
+using teuk_detail::kSourceBatch;
 
 namespace {
 
@@ -44,7 +46,6 @@ namespace {
 #define TEUK_SOURCE_HASH "unversioned"
 #endif
 
-constexpr int kSourceBatch = 256;   // iterations of source windows per compact pass
 constexpr int kPartSteps = 64;      // adjoint iterations whose dL/dA partials are reduced together
 
 }  // namespace
@@ -144,9 +145,10 @@ int check_ctx(const teuk_ctx* c) {
     return TEUK_OK;
 }
 
-// Make the source windows of iteration n resident and return their slot.
+}  // namespace
+
 // Forward stepping fills [n, n + nb); the reverse sweep fills [n - nb + 1, n].
-int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t span, size_t* slot) {
+int teuk_detail::ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t span, size_t* slot) {
     if (!(n >= c->batch_n0 && n < c->batch_n0 + c->batch_len && amp == c->batch_amp)) {
         const int nb = static_cast<int>(span < kSourceBatch ? span : kSourceBatch);
         const int64_t n0 = backward ? n - nb + 1 : n;
@@ -180,6 +182,8 @@ int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t spa
     *slot = static_cast<size_t>(n - c->batch_n0);
     return TEUK_OK;
 }
+
+namespace {
 
 void set_tuning_fields(teuk_ctx* c, int seg, int k) {
     c->seg_rows = seg;
@@ -427,7 +431,9 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
             if (int rc = ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
             if (static_cast<int64_t>(slot) + depth > c->batch_len) {
                 // the block's iterations must share one batch: start a new one at n
+                // (an empty batch: any n would otherwise still count as resident)
                 c->batch_n0 = -1;
+                c->batch_len = 0;
                 if (int rc = ensure_source(c, n, c->amplitude, false, span, &slot)) return rc;
             }
             const size_t wsz = static_cast<size_t>(c->win_r) * c->win_t;

@@ -13,6 +13,8 @@
 
 namespace teuk_detail {
 
+constexpr int kSourceBatch = 256;   // iterations of source windows per compact pass
+
 extern thread_local std::string g_last_error;
 // Record msg as the calling thread's last error and return code.
 int fail(int code, const std::string& msg);
@@ -20,6 +22,12 @@ int hip_fail(hipError_t e, const char* what);
 
 // Release every device resource of a context and delete it (no ownership check).
 void destroy_ctx(teuk_ctx* c);
+
+// Make the source windows of iteration n resident and return their slot in
+// the context's window tables: a source pass over [n, n + nb) (forward) or
+// [n - nb + 1, n] (backward), nb = min(span, one source batch), unless the
+// resident batch already holds n at amplitude amp.
+int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t span, size_t* slot);
 
 }  // namespace teuk_detail
 

@@ -52,6 +52,13 @@ struct BatchInstance {
     int cur;                    // level holding u at the launch's first iteration
     int tile0;                  // index of its strip 0 in the tile list
     double2* wave;              // [rounds][nth] extraction rows, or null
+    // source of the launch's iterations, or all null: iteration n of the
+    // launch uses the windows fh + n * win_r * win_t, fn + n * win_r * win_t
+    // and the origins org[n]
+    const double2* fh;
+    const double2* fn;
+    const int4* org;
+    int win_r, win_t;
 };
 
 struct BatchParams {

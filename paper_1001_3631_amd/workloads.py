@@ -51,6 +51,15 @@ HBM_PLAIN = dict(  # forced EMRI physics on a 12800 x 256 grid (larger than the 
 )
 
 
+ALL_M = dict(  # every m of one circular orbit on the EMRI grid, stepped as one batch
+    name="all_m_6400x128",
+    # cfl 0.25: the m = 3, 4 modes need it (as in the batched instances below)
+    grids=[dict(KERR_EMRI["grid"], m=m, cfl=0.25) for m in (1, 2, 3, 4)],
+    steps=4000,
+    source=dict(KERR_EMRI["source"]),
+)
+
+
 def batched_instances(seed=3, n=64):
     """64 independent evolutions: m uniform in {1,2,3,4}, a uniform in [0, 0.99],
     grid level uniform in {0..3} (1600*2^l x 32*2^l), pulse centre uniform in

@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 from oracle import teuk_oracle as T
 from paper_1001_3631_amd import workloads as W
 
-from test_gpu_parity import STEP_GRIDS, gpu_engine, host, rel, to_dev
+from test_gpu_parity import SRC, STEP_GRIDS, gpu_engine, gpu_source, host, oracle_source, rel, to_dev
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -144,7 +144,7 @@ def test_batched_workload_subset_bitwise(mode):
         eng.close()
 
 
-def test_batch_rejects_sources_and_bad_arguments():
+def test_batch_rejects_bad_arguments():
     from paper_1001_3631_amd._lib import TeukError
     grids = MIXED[:2]
     b = make_batch(grids)
@@ -154,12 +154,130 @@ def test_batch_rejects_sources_and_bad_arguments():
         b.set_mode(2)
     assert b.mode == 0
     e = b.instances[0]
-    orbit = e.orbit_circular(10.0, 9, M=1.0, a=grids[0]["a"])
+    orbit = e.orbit_circular(10.0, 9, M=1.0, a=grids[0]["a"])      # 4 iterations' worth of samples
     e.set_source(orbit, 1.0, 2.0, 2.0, 8.0)
-    with pytest.raises(TeukError):
-        b.step(2)
+    with pytest.raises(TeukError):                                 # ESTATE: orbit too short
+        b.step(5)
+    assert e.info["steps_done"] == 0 and b.instances[1].info["steps_done"] == 0
     assert e._lib.teuk_destroy(e.ctx) == -1        # TEUK_EINVAL: owned by the batch
     b.close()
+
+
+# Sources in batched instances: every m of one orbit (a, grid shared), one
+# instance on an inspiralling orbit table (r* of the circular orbit drifting
+# inwards), and one without a source.
+def _all_m_grids():
+    base = dict(M=1.0, a=0.7, s=-2, nr=301, nth=33, rs_min=-40.0, rs_max=110.0, cfl=0.5, rs_extract=60.0,
+                ko_eps=0.5)
+    return [dict(base, m=m) for m in (1, 2, 3, 4)] + [dict(base, m=2), dict(base, m=3)]
+
+
+def _orbits(engines, grids, nsamples):
+    out = []
+    for k, (e, g) in enumerate(zip(engines, grids)):
+        if k == len(grids) - 1:
+            out.append(None)                               # no source
+            continue
+        orb = e.orbit_circular(10.0, nsamples, M=g["M"], a=g["a"])
+        if k == len(grids) - 2:                            # inspiralling table
+            orb = orb.copy()
+            orb[:, 0] -= 2e-3 * np.arange(nsamples)
+        out.append(orb)
+    return out
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_batch_with_sources_bitwise_equal_to_single_instances(mode):
+    """300 iterations (two source batches) after 7 of instance 0 alone, so the
+    instances' clocks differ; waveforms and states bitwise equal to each
+    instance stepped alone with the same orbit."""
+    grids = _all_m_grids()
+    nsamples = 2 * 320 + 1
+    states = [W.random_state(g["nth"], g["nr"], seed=61 + k) for k, g in enumerate(grids)]
+    b = make_batch(grids)
+    b.set_mode(mode)
+    orbits = _orbits(b.instances, grids, nsamples)
+    for e, (phi, pi), orb in zip(b.instances, states, orbits):
+        e.set_state(to_dev(phi), to_dev(pi))
+        if orb is not None:
+            e.set_source(orb, 30.0, 2.0, 2.0, 8.0)
+    pre = host(b.instances[0].step(7))
+    ws = b.step(300)
+    b.sync()
+    got = [(host(w),) + tuple(host(x) for x in e.get_state()) for w, e in zip(ws, b.instances)]
+    clocks = [e.info["steps_done"] for e in b.instances]
+    b.close()
+    assert clocks == [307] + [300] * (len(grids) - 1)
+    for k, (g, (phi, pi), orb) in enumerate(zip(grids, states, orbits)):
+        eng = gpu_engine(g)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        if orb is not None:
+            eng.set_source(orb, 30.0, 2.0, 2.0, 8.0)
+        if k == 0:
+            assert np.array_equal(host(eng.step(7)), pre)
+        w = host(eng.step(300))
+        p, q = eng.get_state()
+        eng.close()
+        assert_bitwise(got[k], (w, host(p), host(q)))
+        assert np.max(np.abs(got[k][1])) > 0.0
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_batch_source_instance_against_oracle(mode):
+    """An instance with a circular-orbit source, stepped in a batch, against
+    the oracle directly (relative 1e-13)."""
+    grids = [dict(M=1.0, a=0.6, s=-2, m=2, nr=200, nth=41, rs_min=-20.0, rs_max=40.0, cfl=0.5,
+                  rs_extract=10.0, ko_eps=0.5), MIXED[1]]
+    g = T.Grid(**grids[0])
+    phi, pi = W.random_state(g.nth, g.nr, seed=71)
+    b = make_batch(grids)
+    b.set_mode(mode)
+    e = b.instances[0]
+    e.set_state(to_dev(phi), to_dev(pi))
+    gpu_source(e, grids[0], dict(SRC, amplitude=50.0), 6)
+    w = host(b.step(6)[0])
+    b.sync()
+    p, q = (host(x) for x in e.get_state())
+    b.close()
+    src = oracle_source(g, dict(SRC, amplitude=50.0), 6)
+    rp, rq = phi, pi
+    rw = []
+    for n in range(6):
+        rp, rq = T.step(g, rp, rq, n, src)
+        rw.append(rp[:, g.i_ext])
+    assert rel(p, rp) <= 1e-13
+    assert rel(q, rq) <= 1e-13
+    assert rel(w, np.array(rw)) <= 1e-13
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_all_m_workload_bitwise(mode):
+    """The all-m batch at its real size (m = 1..4 of one orbit on 6400 x 128,
+    each with the orbit's source), 12 iterations from pulses, bitwise equal to
+    each instance stepped alone."""
+    cfg = W.ALL_M
+    src = cfg["source"]
+    b = make_batch(cfg["grids"])
+    b.set_mode(mode)
+    orbits = []
+    for e, g in zip(b.instances, cfg["grids"]):
+        orb = e.orbit_circular(src["r0"], 2 * 12 + 1, M=g["M"], a=g["a"])
+        orbits.append(orb)
+        e.set_source(orb, 50.0, src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+        e.init_pulse(50.0, 4.0, 1.0)
+    ws = b.step(12)
+    b.sync()
+    got = [(host(w),) + tuple(host(x) for x in e.get_state()) for w, e in zip(ws, b.instances)]
+    b.close()
+    for g, orb, g_out in zip(cfg["grids"], orbits, got):
+        eng = gpu_engine(g)
+        eng.set_source(orb, 50.0, src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+        eng.init_pulse(50.0, 4.0, 1.0)
+        w = host(eng.step(12))
+        p, q = eng.get_state()
+        eng.close()
+        assert_bitwise(g_out, (w, host(p), host(q)))
+        assert np.max(np.abs(g_out[1])) > 0.0
 
 
 def test_batch_autotune_restores_states(tmp_path):

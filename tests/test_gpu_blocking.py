@@ -85,13 +85,16 @@ def test_block_against_oracle():
     assert rel(w, np.array(rw)) <= 1e-13
 
 
-def test_block_straddling_a_source_batch():
-    """Source windows are produced 256 iterations at a time; blocks starting at
-    n = 3, 7, ..., 255 put one block across the boundary at 256."""
+@pytest.mark.parametrize("lead", [1, 2, 3])
+def test_block_straddling_a_source_batch(lead):
+    """Source windows are produced 256 iterations at a time; after `lead`
+    single iterations, blocks of 4 start at n = lead + 4j, and the one at
+    252 + lead crosses the boundary at 256, so a new batch starts there (at
+    253, 254 or 255)."""
     grid = STEP_GRIDS[0]
     phi, pi = W.random_state(grid["nth"], grid["nr"], seed=19)
     ref = run(grid, phi, pi, [((4, 1), 300)])
-    got = run(grid, phi, pi, [((4, 1), 3), ((4, 4), 297)])
+    got = run(grid, phi, pi, [((4, 1), lead), ((4, 4), 300 - lead)])
     assert_bitwise(got, ref)
 
 
