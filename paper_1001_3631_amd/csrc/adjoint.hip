@@ -59,15 +59,16 @@ __device__ __forceinline__ int a_xcd_remap(int b, int nwg) {
 }
 
 // weights of the angular operator at an interior row: Ang[f]_j =
-// alpha_j f_{j+1} + beta_j f_j + gamma_j f_{j-1}
+// alpha_j f_{j+1} + beta_j f_j + gamma_j f_{j-1} (the record holds the
+// weights halved; doubling is exact)
 struct AngW {
     double alpha, beta, gamma;
 };
 __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
     AngW w;
-    w.alpha = R.inv_h2 + R.cot2h;
-    w.beta = fma(-2.0, R.inv_h2, -R.V);
-    w.gamma = R.inv_h2 - R.cot2h;
+    w.alpha = 2.0 * (R.inv_2h2 + R.cot4h);
+    w.beta = 2.0 * fma(-2.0, R.inv_2h2, -R.V2);
+    w.gamma = 2.0 * (R.inv_2h2 - R.cot4h);
     return w;
 }
 
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     const int jlo = seg * SEG;
     const int jhi = (seg == P.nseg - 1) ? nth : jlo + SEG;
     const double dt = P.dt, hdt = 0.5 * P.dt, inv_hr = P.inv_hr;
+    const double dt2 = 2.0 * P.dt;   // c.c0 is C_0 / 2: dt C_0 = dt2 c.c0, hdt C_0 = dt c.c0
     const double third = 0.33333333333333331483, four_thirds = 1.3333333333333332593;
 
     int4 org = make_int4(0, 0, 0, 0);
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 nD[k] = make_double2(dt * fma(-c.b, p.x, mrq.x), dt * fma(-c.b, p.y, mrq.y));   // -> dPhi
                 nDQ[k] = make_double2(dt * c.b * q.x, dt * c.b * q.y);                // -> dPi
                 const double2 c0q = cmul_conj(c.c0, q);
-                nC[k] = make_double2(dt * c0q.x, dt * c0q.y);                         // -> Phi~ (row r)
+                nC[k] = make_double2(dt2 * c0q.x, dt2 * c0q.y);                       // -> Phi~ (row r)
                 nW[k] = make_double2(dt * c.w * q.x, dt * c.w * q.y);                 // -> Ang^T
                 if (SRC && r >= jlo && r < jhi_ && writer) {
                     const double2 F = src_at(P.fn, org.z, org.w, P.win_r, P.win_t, i, r);
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 // Phi^h = Phi~ + hdt (Pi~ - b dPhi);  Pi^h = Pi~ + hdt (b dPi + S)
                 yW[k] = make_double2(hdt * c.w * q.x, hdt * c.w * q.y);
                 const double2 c0q = cmul_conj(c.c0, q);
-                cC[k] = make_double2(fma(hdt, c0q.x, p.x), fma(hdt, c0q.y, p.y));
+                cC[k] = make_double2(fma(dt, c0q.x, p.x), fma(dt, c0q.y, p.y));
                 const double2 ctq = cmul_conj(c.ct, q);
                 qb[k] = make_double2(fma(hdt, p.x - ctq.x, q.x), fma(hdt, p.y - ctq.y, q.y));
                 const double2 mrq = cmul_conj(c.mr, q);

@@ -108,8 +108,9 @@ std::string build_geometry(double M, double a, int s, int m, int nr, int nth,
         set(RF_CT_I1, 2.0 * s * a * Delta);
         // C_0 numerator: (3 Delta/r^2)(2 Delta + (1+s) r Delta') + i(2 m a s Delta' + 6 m a Delta / r),
         // with 2 Delta + (1+s) r Delta' = 2(2+s) r^2 - 2(3+s) M r + 2 a^2
-        set(RF_C0_RE, (3.0 * Delta / (r * r)) * (2.0 * (2.0 + s) * r * r - 2.0 * (3.0 + s) * M * r + 2.0 * a * a));
-        set(RF_C0_IM, 2.0 * m * a * s * dDelta + 6.0 * m * a * Delta / r);
+        // C_0 numerators, halved (see ThetaRow)
+        set(RF_C0_RE, 0.5 * ((3.0 * Delta / (r * r)) * (2.0 * (2.0 + s) * r * r - 2.0 * (3.0 + s) * M * r + 2.0 * a * a)));
+        set(RF_C0_IM, 0.5 * (2.0 * m * a * s * dDelta + 6.0 * m * a * Delta / r));
         // m_r = b c_t + C_r - b d_r* b collected over Sigma^4:
         //   Re: q^2 Delta [4(s+2) r + 6 a^2/r] - a^2 Delta sin^2 [q ct_re/(q + Sigma) + q((s+1/2) Delta' + 6 Delta/r)]
         //   Im: b Im(c_t) + 2 m a q / Sigma^2
@@ -132,15 +133,15 @@ std::string build_geometry(double M, double a, int s, int m, int nr, int nth,
         ThetaRow& R = G.rows[j];
         const double th = j * hh;
         R.theta = th;
-        R.inv_h2 = 1.0 / (hh * hh);
+        R.inv_2h2 = 0.5 * (1.0 / (hh * hh));
         R.cos_th = std::cos(th);
         const double sn = std::sin(th);
         R.sin2 = sn * sn;
         if (j > 0 && j < nth - 1) {
             const double cot = R.cos_th / sn;
             const double V = (m + s * R.cos_th) * (m + s * R.cos_th) / (sn * sn) - s;
-            R.cot2h = cot / (2.0 * hh);
-            R.V = V;
+            R.cot4h = 0.5 * (cot / (2.0 * hh));
+            R.V2 = 0.5 * V;
         }
         R.prof = std::pow(2.0, 0.5 * (p + qq)) * std::pow(std::sin(0.5 * th), p) *
                  std::pow(std::cos(0.5 * th), qq);

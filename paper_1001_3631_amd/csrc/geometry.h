@@ -8,7 +8,7 @@
 //   b   = q g                                   (q = r^2 + a^2)
 //   w   = Delta g^2
 //   c_t = [ct_re + i (ct_i0 + ct_i1 cos)] g^2
-//   C_0 = [c0_re + i c0_im] g^2
+//   C_0 = [c0_re + i c0_im] g^2   (the record holds half of c0_re, c0_im)
 //   Re m_r = [mr_p - a^2 Delta sin^2 (mr_k1/(q + Sigma) + mr_k2)] g^4
 //   Im m_r = b Im c_t + mr_b g^2
 // so the device keeps one radial record per node / half node and one angular
@@ -31,13 +31,17 @@ enum RField {
 };
 
 // One angular record per row (array-of-structs, 8 doubles = 64 bytes).
-// Pole rows (j = 0, nth-1) leave cot2h and V at zero: they are never evolved.
+// Pole rows (j = 0, nth-1) leave cot4h and V2 at zero: they are never evolved.
+// The angular operator's weights are stored halved, and so is C_0 in the
+// radial record: the stencil applies them to column sums (twice the
+// averages), and scaling by a power of two commutes with rounding, so the
+// products are the same numbers without the multiplications by 1/2.
 struct ThetaRow {
     double cos_th;   // cos(theta_j)
     double sin2;     // sin^2(theta_j)
-    double cot2h;    // cot(theta_j) / (2 h_th)
-    double V;        // angular potential (m + s cos)^2 / sin^2 - s
-    double inv_h2;   // 1 / h_th^2
+    double cot4h;    // cot(theta_j) / (4 h_th), half the first-difference weight
+    double V2;       // half the angular potential ((m + s cos)^2 / sin^2 - s) / 2
+    double inv_2h2;  // 1 / (2 h_th^2), half the second-difference weight
     double theta;    // theta_j
     double prof;     // initial angular profile P(theta_j)
     double pad;      // keeps the record at 64 bytes

@@ -59,7 +59,8 @@ struct Coef {
     double2 ct, mr, c0;
 };
 
-// b = q g, w = Delta g^2, c_t, C_0 = numerators g^2, g = 1/Sigma,
+// b = q g, w = Delta g^2, c_t, C_0 = numerators g^2, g = 1/Sigma (the C_0
+// numerators, and so c.c0, are stored halved: see ThetaRow),
 // Re m_r = [mr_p - a^2 Delta sin^2 (mr_k1/(q + Sigma) + mr_k2)] g^4,
 // Im m_r = b Im c_t + mr_b g^2.  For a = 0 the bracket's second term is zero
 // and the division is skipped; kerr (a != 0) is the same for every point of
@@ -103,7 +104,8 @@ __device__ __forceinline__ double2 masked(bool keep, double2 v) {
 //   sQ0           : Pi_left + Pi_right     (row j)
 //   dP0, dQ0      : right - left           (row j)
 // With averages Phi~ = sP/2, Pi~ = sQ0/2 and differences dPhi = dP0/h_r,
-// dPi = dQ0/h_r:
+// dPi = dQ0/h_r (the halvings of the C_0 and angular terms sit in the
+// halved c.c0 and angular weights):
 //   S_Pi  = -c_t Pi~ + m_r dPhi + C_0 Phi~ + w Ang_h[Phi~] + F
 //   Phi'  = basePhi + tau (Pi~ - b dPhi)          (S_Phi = Pi~, D = diag(b, -b))
 //   Pi'   = basePi  + tau (b dPi + S_Pi)
@@ -117,16 +119,16 @@ __device__ __forceinline__ void lw_point(const Coef& c, const ThetaRow& R,
                                          double tau, double inv_hr,
                                          double2 basePhi, double2 basePi,
                                          double2& outPhi, double2& outPi) {
-    const double2 P = c_scale(0.5, sP0);
     const double2 Q = c_scale(0.5, sQ0);
     const double2 dP = c_scale(inv_hr, dP0);
     const double2 dQ = c_scale(inv_hr, dQ0);
     double2 ang;
     {
-        const double d2x = (sPp.x - 2.0 * sP0.x) + sPm.x, d2y = (sPp.y - 2.0 * sP0.y) + sPm.y;
+        // 2 sP0 is exact, so the fma rounds as the subtraction would
+        const double d2x = fma(-2.0, sP0.x, sPp.x) + sPm.x, d2y = fma(-2.0, sP0.y, sPp.y) + sPm.y;
         const double d1x = sPp.x - sPm.x, d1y = sPp.y - sPm.y;
-        ang.x = 0.5 * fma(-R.V, sP0.x, fma(R.cot2h, d1x, d2x * R.inv_h2));
-        ang.y = 0.5 * fma(-R.V, sP0.y, fma(R.cot2h, d1y, d2y * R.inv_h2));
+        ang.x = fma(-R.V2, sP0.x, fma(R.cot4h, d1x, d2x * R.inv_2h2));
+        ang.y = fma(-R.V2, sP0.y, fma(R.cot4h, d1y, d2y * R.inv_2h2));
     }
     double2 S;
     S.x = fma(c.w, ang.x, F.x);
@@ -141,11 +143,11 @@ __device__ __forceinline__ void lw_point(const Coef& c, const ThetaRow& R,
     S.x = fma(-c.mr.y, dP.y, S.x);
     S.y = fma(c.mr.x, dP.y, S.y);
     S.y = fma(c.mr.y, dP.x, S.y);
-    // + C_0 Phi~
-    S.x = fma(c.c0.x, P.x, S.x);
-    S.x = fma(-c.c0.y, P.y, S.x);
-    S.y = fma(c.c0.x, P.y, S.y);
-    S.y = fma(c.c0.y, P.x, S.y);
+    // + C_0 Phi~ = (C_0 / 2) sP0
+    S.x = fma(c.c0.x, sP0.x, S.x);
+    S.x = fma(-c.c0.y, sP0.y, S.x);
+    S.y = fma(c.c0.x, sP0.y, S.y);
+    S.y = fma(c.c0.y, sP0.x, S.y);
     outPhi.x = fma(tau, fma(-c.b, dP.x, Q.x), basePhi.x);
     outPhi.y = fma(tau, fma(-c.b, dP.y, Q.y), basePhi.y);
     outPi.x = fma(tau, fma(c.b, dQ.x, S.x), basePi.x);
