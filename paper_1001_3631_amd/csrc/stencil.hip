@@ -108,9 +108,20 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
 #pragma unroll
         for (int t = 0; t < PF && t < NT; ++t) fetch(t);
 
+        // Angular records: the half step of iteration t uses row jlo-3+t, the
+        // full step of iteration t the row of the half step of t-1.  Each is
+        // read once, one iteration before its first use (scalar loads).
+        ThetaRow Rh[SEG + 6];
+        auto fetch_row = [&](int t) {
+            const int jr = FAST ? jlo - 3 + t : min(max(jlo - 3 + t, 0), nth - 1);
+            Rh[t] = rows[jr];
+        };
+        if (2 < NT) fetch_row(2);
+
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t + PF < NT) fetch(t + PF);
+            if (t >= 1 && t + 1 < NT) fetch_row(t + 1);
             const int jj = jlo - 2 + t;
             if (FAST || jj <= jhi + 1) {
                 // ---- row jj of u^n and its column sums/differences ----
@@ -133,7 +144,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
                     hP[t - 1] = z;
                     hQ[t - 1] = z;
                     if (FAST || (jh >= 1 && jh <= nth - 2)) {
-                        const ThetaRow R = rows[jh];
+                        const ThetaRow& R = Rh[t];
                         const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                         const double2 F =
                             SRC ? masked(colh && static_cast<unsigned>(jh - org.y) < static_cast<unsigned>(P.win_t),
@@ -163,7 +174,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
                         double2 oP = z, oQ = z;
                         const bool pole = !FAST && ((jf == 0) || (jf == nth - 1));
                         if (FAST || (!pole && interior_col)) {
-                            const ThetaRow R = rows[jf];
+                            const ThetaRow& R = Rh[t - 1];
                             const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                             const double2 F =
                                 SRC ? masked(coln && static_cast<unsigned>(jf - org.w) < static_cast<unsigned>(P.win_t),

@@ -190,9 +190,20 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
 #pragma unroll
     for (int t = 0; t < PF && t < NT; ++t) fetch(t);
 
+    // Angular records: the half step of iteration t uses row lo-3+t, the full
+    // step of iteration t the row of the half step of t-1.  Each is read
+    // once, one iteration before its first use.
+    ThetaRow Rh[NROW + 4];
+    auto fetch_row = [&](int t) {
+        const int jr = FAST ? lo - 3 + t : min(max(lo - 3 + t, 0), nth - 1);
+        Rh[t] = rows[jr];
+    };
+    if (2 < NT) fetch_row(2);
+
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (!IN_LDS && t + PF < NT) fetch(t + PF);
+        if (t >= 1 && t + 1 < NT) fetch_row(t + 1);
         const int jj = lo - 2 + t;
         if (FAST || jj <= hi + 1) {
             // ---- row jj of the input level and its column sums/differences ----
@@ -220,7 +231,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                 hP[t - 1] = z;
                 hQ[t - 1] = z;
                 if (FAST || (jh >= 1 && jh <= nth - 2)) {
-                    const ThetaRow R = rows[jh];
+                    const ThetaRow& R = Rh[t];
                     const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                     const double2 F = SRC ? window_value(A.fh, A.org.x, A.org.y, P.win_r, P.win_t, i, jh) : z;
                     lw_point(c, R, sP[t - 2], sP[t - 1], sP[t], sQ[t - 1],
@@ -247,7 +258,7 @@ __device__ __forceinline__ void stream_level(const StepParams P, const LevelArgs
                     double2 oP = z, oQ = z;
                     const bool pole = !FAST && ((jf == 0) || (jf == nth - 1));
                     if (FAST || (!pole && interior_col)) {
-                        const ThetaRow R = rows[jf];
+                        const ThetaRow& R = Rh[t - 1];
                         const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                         const double2 F = SRC ? window_value(A.fn, A.org.z, A.org.w, P.win_r, P.win_t, i, jf) : z;
                         // sums/differences of the half values at i+1/2 (own) and i-1/2 (lane-1)
