@@ -485,6 +485,7 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
     // save every instance's current level, time each variant, restore
     const int seg0 = b->seg_rows, mode0 = b->mode;
     std::vector<double2*> save;
+    hipError_t e = hipSuccess;
     auto release = [&]() {
         for (double2* p : save) (void)hipFree(p);
         save.clear();
@@ -493,14 +494,18 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
         const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
         for (int f = 0; f < 2; ++f) {
             double2* p = nullptr;
-            hipError_t e = hipMalloc(&p, bytes);
+            e = hipMalloc(&p, bytes);
             if (e != hipSuccess) {
                 release();
                 return fail(TEUK_ENOMEM, std::string("batch autotune planes: ") + hipGetErrorString(e));
             }
             save.push_back(p);
-            HIP_TRY(hipMemcpyAsync(p, c->plane[c->cur][f], bytes, hipMemcpyDeviceToDevice, b->stream),
-                    "batch autotune save");
+            e = hipMemcpyAsync(p, c->plane[c->cur][f], bytes, hipMemcpyDeviceToDevice, b->stream);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(b->stream);
+                release();
+                return hip_fail(e, "batch autotune save");
+            }
         }
     }
     // sources are detached while timing (the compact source pass is a small
@@ -530,7 +535,7 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
         release();
     };
     hipEvent_t ev[2] = {nullptr, nullptr};
-    hipError_t e = hipEventCreate(&ev[0]);
+    e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e != hipSuccess) {
         restore();
