@@ -126,10 +126,24 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     double2 hP[NT], hQ[NT];          // half-level lambda at i+1/2 (unfolded)
     double2 yW[NT], cC[NT], qb[NT], dp[NT], dq[NT];    // half-level sources
 
+    // Angular records of rows jlo-4+u: every stage at iteration it reads
+    // rows at fixed offsets from its k, the newest being u = it - 2 (stage
+    // 2/3).  For SEG <= 4 each is read once, one iteration before that first
+    // use, into scalar registers (for longer segments the window's scalar
+    // registers spill and each record is read where it is used).
+    constexpr bool WINDOW = SEG <= 4;
+    ThetaRow Rw[NT];
+    auto fetch_rec = [&](int u) {
+        const int row = jlo - 4 + u;
+        Rw[u] = rows[FAST ? row : min(max(row, 0), nth - 1)];
+    };
+    auto rec = [&](int u) -> ThetaRow { return WINDOW ? Rw[u] : rows[jlo - 4 + u]; };
+
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
         const int jj = jlo - 4 + it;
         if (FAST ? it > SEG + 9 : jj > jhi + 5) continue;
+        if (WINDOW && it >= 1) fetch_rec(it - 1);
         // ---- 1. load lambda^{n+1}(i, jj) ----
         {
             double2 p = cz(), q = cz();
@@ -160,7 +174,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             mQ[k] = q;
             nQ[k] = nD[k] = nDQ[k] = nC[k] = nW[k] = cz();
             if (FAST || (interior_row && interior_col)) {
-                const ThetaRow R = rows[r];
+                const ThetaRow R = rec(k);
                 const Coef c = coef_at(rn, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi' = Phi + dt (Pi~ - b dPhi);  Pi' = Pi + dt (b dPi + S),
                 // S = -c_t Pi~ + m_r dPhi + C_0 Phi~ + w Ang[Phi~] + F
@@ -185,9 +199,9 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             double2 ptil = cz();
             if (FAST || (r1 >= 0 && r1 < nth)) {
                 ptil = nC[k];
-                if (FAST || r1 - 1 >= 1) ptil = axpy(ang_weights(rows[r1 - 1]).alpha, nW[k - 1], ptil);
-                if (FAST || (r1 >= 1 && r1 <= nth - 2)) ptil = axpy(ang_weights(rows[r1]).beta, nW[k], ptil);
-                if (FAST || r1 + 1 <= nth - 2) ptil = axpy(ang_weights(rows[r1 + 1]).gamma, nW[k + 1], ptil);
+                if (FAST || r1 - 1 >= 1) ptil = axpy(ang_weights(rec(k - 1)).alpha, nW[k - 1], ptil);
+                if (FAST || (r1 >= 1 && r1 <= nth - 2)) ptil = axpy(ang_weights(rec(k)).beta, nW[k], ptil);
+                if (FAST || r1 + 1 <= nth - 2) ptil = axpy(ang_weights(rec(k + 1)).gamma, nW[k + 1], ptil);
             }
             // contributions of node i to its right half (i+1/2) and left half (i-1/2)
             const double2 a = make_double2(0.5 * ptil.x, 0.5 * ptil.y);
@@ -217,7 +231,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                     if (r2 == nth - 2) { p = axpy(four_thirds, hP[k + 1], p); q = axpy(four_thirds, hQ[k + 1], q); }
                     if (r2 == nth - 3) { p = axpy(-third, hP[k + 2], p); q = axpy(-third, hQ[k + 2], q); }
                 }
-                const ThetaRow R = rows[r2];
+                const ThetaRow R = rec(k);
                 const Coef c = coef_at(rh, R.cos_th, R.sin2, P.kerr != 0);
                 // Phi^h = Phi~ + hdt (Pi~ - b dPhi);  Pi^h = Pi~ + hdt (b dPi + S)
                 yW[k] = make_double2(hdt * c.w * q.x, hdt * c.w * q.y);
@@ -241,9 +255,9 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
             double2 pb = cz();
             if (FAST || (r3 >= 0 && r3 < nth)) {
                 pb = cC[k];
-                if (FAST || r3 - 1 >= 1) pb = axpy(ang_weights(rows[r3 - 1]).alpha, yW[k - 1], pb);
-                if (FAST || (r3 >= 1 && r3 <= nth - 2)) pb = axpy(ang_weights(rows[r3]).beta, yW[k], pb);
-                if (FAST || r3 + 1 <= nth - 2) pb = axpy(ang_weights(rows[r3 + 1]).gamma, yW[k + 1], pb);
+                if (FAST || r3 - 1 >= 1) pb = axpy(ang_weights(rec(k - 1)).alpha, yW[k - 1], pb);
+                if (FAST || (r3 >= 1 && r3 <= nth - 2)) pb = axpy(ang_weights(rec(k)).beta, yW[k], pb);
+                if (FAST || r3 + 1 <= nth - 2) pb = axpy(ang_weights(rec(k + 1)).gamma, yW[k + 1], pb);
             }
             // half i+1/2 gives its left node (i) 1/2 avg - diff/h, its right node (i+1) 1/2 avg + diff/h
             const double2 hpP = make_double2(0.5 * pb.x, 0.5 * pb.y);
