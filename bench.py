@@ -22,12 +22,18 @@ Also reported on the same JSON line:
   all_m         every m (1..4) of one circular orbit on the 6400 x 128 grid,
                 each with its source, 4000 iterations as one batch, against
                 the same instances one after another;
+  adjoint_at_scale
+                16 instances on 12800 x 256 with eccentric orbits (seeded a,
+                m, p, e), forward + checkpointed adjoint one instance after
+                another (2000 iterations each by default; 50000 with
+                --scale-iterations 50000);
   cpu_baseline  the FP64 oracle on the host for a bounded number of
                 iterations of the same workload.
 """
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -69,6 +75,10 @@ def parse():
     ap.add_argument("--all-m-iterations", type=int, default=None,
                     help="iterations of the all-m batch (default: the workload's 4000)")
     ap.add_argument("--batched-iterations", type=int, default=10000)
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the forward + checkpointed adjoint of the 16 instances on 12800 x 256")
+    ap.add_argument("--scale-iterations", type=int, default=2000,
+                    help="iterations per instance of that workload (its full length is 50000)")
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
     ap.add_argument("--tuning", default=None,
@@ -157,6 +167,73 @@ def adjoint_ratio(args):
             "forward_s": round(tf, 4), "adjoint_s": round(ta, 4),
             "ratio": round(ta / tf, 3), "forward_plus_backward_with_recompute_s": round(tc, 4),
             "ratio_with_recompute": round((tc - tf) / tf, 3)}
+
+
+def adjoint_at_scale(args):
+    """Forward + checkpointed adjoint of the 16 eccentric-orbit instances on
+    12800 x 256 (seeded a, m, p, e, anomaly), one instance after another:
+    each alone fills the GPU (51200 waves per launch).  Per instance: the
+    orbit table, the forward keeping a snapshot every ceil(sqrt(N))
+    iterations, and the backward recomputing every segment from its snapshot
+    while sweeping it in reverse.  Loss sum |w - y|^2 against the waveform of
+    source amplitude 0.9 (zero initial data, so y = 0.9 w and dL/dA =
+    0.2 |w|^2 exactly: checked)."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    from paper_1001_3631_amd.engine import Engine
+    cfg = W.ADJOINT_AT_SCALE
+    n = args.scale_iterations or cfg["steps"]
+    src = cfg["source"]
+    tf = tb = 0.0
+    pts = 0
+    worst_dA = 0.0
+    snap_bytes = peak_used = 0
+    tuning = None
+    for k, inst in enumerate(W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])):
+        g, o = inst["grid"], inst["orbit"]
+        free0, _ = torch.cuda.mem_get_info()
+        eng = Engine(**g)
+        orbit = eng.orbit_eccentric(o["p"], o["e"], 2 * n + 1, M=g["M"], a=g["a"], chi0=o["chi0"])
+        eng.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"],
+                       src["cutoff_sigmas"])
+        if tuning is None:
+            eng.autotune(None)              # same shape for every instance: tune once (untimed)
+            tuning = eng.tuning
+        else:
+            eng.set_tuning(tuning["seg_rows"], tuning["k_steps"])
+        z = torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda")
+        eng.set_state(z, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, _ = eng.forward_checkpointed(n, interval=0, force_recompute=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        free1, _ = torch.cuda.mem_get_info()
+        gw = ((2.0 * (1.0 - cfg["target_amplitude"])) * w).contiguous()
+        gp, gq, dA = eng.backward_checkpointed(gw, 0.0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        eng.check_finite()
+        ref = 2.0 * (1.0 - cfg["target_amplitude"]) * float(torch.sum(torch.abs(w) ** 2))
+        worst_dA = max(worst_dA, abs(dA - ref) / max(abs(ref), 1e-300))
+        tf += t1 - t0
+        tb += t2 - t1
+        pts += g["nr"] * g["nth"] * n
+        interval = math.ceil(math.sqrt(n))
+        snap_bytes = max(snap_bytes, -(-n // interval) * 2 * g["nr"] * g["nth"] * 16)
+        peak_used = max(peak_used, free0 - free1)
+        print(f"[bench] adjoint_at_scale instance {k}: a={g['a']:.3f} m={g['m']} p={o['p']:.2f} "
+              f"e={o['e']:.3f} fwd {t1 - t0:.3f} s bwd {t2 - t1:.3f} s dA {dA:.6e}", file=sys.stderr,
+              flush=True)
+        del gp, gq, gw, w, z
+        eng.close()
+    return {"workload": cfg["name"], "instances": cfg["instances"], "iterations": n,
+            "tuning": tuning, "forward_s": round(tf, 3), "backward_with_recompute_s": round(tb, 3),
+            "ratio_backward_over_forward": round(tb / tf, 3),
+            "forward_gpts": round(pts / tf / 1e9, 3),
+            "snapshot_bytes_per_instance": int(snap_bytes),
+            "device_bytes_used_per_instance": int(peak_used),
+            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}")}
 
 
 def batched(args):
@@ -394,6 +471,10 @@ def main():
         print(f"[bench] batched: {extra['batched']}", file=sys.stderr, flush=True)
         extra["all_m"] = all_m(args)
         print(f"[bench] all_m: {extra['all_m']}", file=sys.stderr, flush=True)
+
+    if not args.no_scale:
+        extra["adjoint_at_scale"] = adjoint_at_scale(args)
+        print(f"[bench] adjoint_at_scale: {extra['adjoint_at_scale']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

@@ -134,6 +134,19 @@ int teuk_set_amplitude(teuk_ctx* ctx, double amplitude);
  * phi~_p = Omega t_k, Omega = M^{1/2}/(r0^{3/2} + a M^{1/2}).  out has 3*nsamples doubles. */
 int teuk_orbit_circular(double M, double a, double r0, double dt, int64_t nsamples, double* out);
 
+/* Fill a host array with a bound prograde equatorial Kerr geodesic of
+ * semi-latus rectum p and eccentricity e (r = p/(1 + e cos chi), chi = 0 at
+ * periapsis, chi = chi0 at t = 0), sampled at t_k = k dt/2,
+ * k = 0..nsamples-1: r*_p, theta_p = pi/2, and phi~_p with phase zero at
+ * t = 0 (d phi~ = d phi + a/Delta dr, the azimuth of Sec. 3.2).  The orbit
+ * is the input of the synthetic source, which stands in for the paper's T.
+ * E and L are closed-form; t(chi) and phi(chi) are cosine series of the
+ * geodesic rates (accurate to rounding for e <= 0.9), inverted by Newton's
+ * method.  TEUK_EINVAL for |a| >= M, e outside [0, 0.9], dt <= 0, or p and
+ * e with no bound stable prograde orbit.  out has 3*nsamples doubles. */
+int teuk_orbit_eccentric(double M, double a, double p, double e, double chi0, double dt, int64_t nsamples,
+                         double* out);
+
 /* Take nsteps iterations (lw1, boundary rows of the half step, lw2 with the
  * source and dissipation, boundary conditions).  If waveform_dev is not NULL
  * it receives nsteps*nth complex128: row n is Phi at the extraction column

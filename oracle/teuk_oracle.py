@@ -50,7 +50,8 @@ import numpy as np
 
 __all__ = [
     "horizons", "tortoise_of_x", "x_of_tortoise", "coefficients",
-    "angular_potential", "Grid", "Source", "circular_orbit", "initial_pulse",
+    "angular_potential", "Grid", "Source", "circular_orbit", "equatorial_constants",
+    "equatorial_rates", "eccentric_orbit", "initial_pulse",
     "apply_bc", "step", "evolve", "adjoint_step", "adjoint_evolve",
     "waveform_loss", "assemble_step_matrix",
 ]
@@ -263,6 +264,122 @@ def circular_orbit(M, a, r0, dt, nsteps):
     t = np.arange(2 * nsteps + 1) * (0.5 * dt)
     return {"rs": np.full(t.shape, rs_p), "th": np.full(t.shape, 0.5 * np.pi),
             "phi": Omega * t, "Omega": Omega}
+
+
+def _kerr_R(r, E, L, a):
+    """Equatorial radial geodesic potential (M = 1, Carter constant 0):
+    R(r) = [E(r^2+a^2) - a L]^2 - Delta [r^2 + (L - a E)^2], with
+    (r^2 dr/dtau)^2 = R(r)."""
+    delta = r * r - 2.0 * r + a * a
+    P = E * (r * r + a * a) - a * L
+    return P * P - delta * (r * r + (L - a * E) ** 2)
+
+
+def equatorial_constants(a, p, e):
+    """Energy E, angular momentum L and third root r_3 of a bound prograde
+    equatorial Kerr geodesic with periapsis p/(1+e) and apoapsis p/(1-e)
+    (M = 1).  Defined by R vanishing at both turning points (for e = 0: a
+    double root, R(p) = R'(p) = 0), solved by a library root finder started
+    from the Schwarzschild values.  r_3 is the remaining positive root of
+    R(r)/r, a cubic."""
+    import warnings
+
+    from scipy.optimize import fsolve
+
+    rp_, ra_ = p / (1.0 + e), p / (1.0 - e)
+    E0 = np.sqrt(((p - 2.0) ** 2 - 4.0 * e * e) / (p * (p - 3.0 - e * e)))
+    L0 = p / np.sqrt(p - 3.0 - e * e)
+    if e > 0.0:
+        def eqs(v):
+            return [_kerr_R(rp_, v[0], v[1], a) / rp_ ** 4, _kerr_R(ra_, v[0], v[1], a) / ra_ ** 4]
+    else:
+        def eqs(v):
+            h = 1e-4 * p
+            dR = (_kerr_R(p + h, v[0], v[1], a) - _kerr_R(p - h, v[0], v[1], a)) / (2.0 * h)
+            return [_kerr_R(p, v[0], v[1], a) / p ** 4, dR / p ** 3]
+    with warnings.catch_warnings():   # at full precision fsolve reports that it cannot improve
+        warnings.simplefilter("ignore", RuntimeWarning)
+        E, L = fsolve(eqs, [E0, L0], xtol=1e-15)
+    if e == 0.0:
+        # R'(p) by a central difference is exact for the quartic up to an
+        # O(h^2) term that the double root makes vanish to rounding; polish
+        # with the exact derivative.
+        def eqs2(v):
+            E_, L_ = v
+            P = E_ * (p * p + a * a) - a * L_
+            delta = p * p - 2.0 * p + a * a
+            dR = 4.0 * E_ * p * P - (2.0 * p - 2.0) * (p * p + (L_ - a * E_) ** 2) - delta * 2.0 * p
+            return [_kerr_R(p, E_, L_, a) / p ** 4, dR / p ** 3]
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            E, L = fsolve(eqs2, [E, L], xtol=1e-15)
+    # R(r)/r = (E^2-1) r^3 + 2 r^2 - (a^2 + x^2 + 2 a x E) r + 2 x^2, x = L - a E
+    x = L - a * E
+    roots = np.roots([E * E - 1.0, 2.0, -(a * a + x * x + 2.0 * a * x * E), 2.0 * x * x])
+    roots = np.sort(np.real(roots[np.abs(np.imag(roots)) < 1e-6 * p]))
+    r3 = float(roots[0])
+    return float(E), float(L), r3
+
+
+def equatorial_rates(a, p, e, E, L, r3, chi):
+    """dt/dchi and dphi/dchi along the orbit r = p/(1 + e cos chi) (M = 1).
+    From the geodesic equations r^2 dt/dtau = a(L - aE) + (r^2+a^2) P/Delta,
+    r^2 dphi/dtau = (L - aE) + a P/Delta, P = E(r^2+a^2) - aL, and
+    dtau/dchi = (dr/dchi) r^2/sqrt(R) with R = (1-E^2) r (r_a - r)(r - r_p)(r - r_3),
+    in which (dr/dchi)/sqrt((r_a - r)(r - r_p)) = sqrt(1-e^2)/(1 + e cos chi)."""
+    chi = np.asarray(chi, dtype=np.float64)
+    den = 1.0 + e * np.cos(chi)
+    r = p / den
+    delta = r * r - 2.0 * r + a * a
+    P = E * (r * r + a * a) - a * L
+    dtau = r * r * np.sqrt(1.0 - e * e) / (den * np.sqrt((1.0 - E * E) * r * (r - r3)))
+    vt = (a * (L - a * E) + (r * r + a * a) * P / delta) / (r * r) * dtau
+    vphi = ((L - a * E) + a * P / delta) / (r * r) * dtau
+    return vt, vphi, dtau
+
+
+def eccentric_orbit(M, a, p, e, chi0, dt, nsteps):
+    """Bound prograde equatorial Kerr orbit (semi-latus rectum p, eccentricity
+    e, relativistic anomaly chi0 at t = 0, chi = 0 at periapsis) sampled at
+    t_k = k dt/2, k = 0..2*nsteps: (r*_p, theta_p, phi~_p).
+
+    t(chi) and phi(chi) are integrated by adaptive quadrature from sample to
+    sample, and chi at each t_k is found by Newton's method on t(chi) - t_k
+    (dt/dchi > 0).  phi~ = phi + a/(r_+ - r_-) ln((r - r_+)/(r - r_-)) is the
+    azimuth of Sec. 3.2 (d phi~ = d phi + a/Delta dr), with phase zero at t = 0.
+    Lengths and times in units of M."""
+    from scipy.integrate import quad
+
+    a_, p_ = a / M, p / M
+    E, L, r3 = equatorial_constants(a_, p_, e)
+    vt = lambda c: float(equatorial_rates(a_, p_, e, E, L, r3, c)[0])
+    vp = lambda c: float(equatorial_rates(a_, p_, e, E, L, r3, c)[1])
+    rp, rm = horizons(1.0, a_)
+
+    def phitilde_shift(r):
+        return a_ / (rp - rm) * np.log((r - rp) / (r - rm))
+
+    n = 2 * nsteps + 1
+    h = 0.5 * dt / M
+    chis = np.empty(n)
+    phis = np.empty(n)
+    chis[0], phis[0] = chi0, 0.0
+    for k in range(1, n):
+        c0 = chis[k - 1]
+        c = c0 + h / vt(c0)
+        for _ in range(50):
+            f = quad(vt, c0, c, epsabs=0.0, epsrel=2e-14, limit=200)[0] - h
+            dc = f / vt(c)
+            c -= dc
+            if abs(dc) <= 1e-16 * max(1.0, abs(c)):
+                break
+        chis[k] = c
+        phis[k] = phis[k - 1] + quad(vp, c0, c, epsabs=0.0, epsrel=2e-14, limit=200)[0]
+    r = p_ / (1.0 + e * np.cos(chis))
+    rs = tortoise_of_x((r - rp) * M, M, a)
+    phit = phis + phitilde_shift(r) - phitilde_shift(r[0])
+    return {"rs": np.asarray(rs, dtype=np.float64), "th": np.full(n, 0.5 * np.pi), "phi": phit,
+            "chi": chis, "r": r * M, "E": E, "L": L, "r3": r3}
 
 
 class Source:

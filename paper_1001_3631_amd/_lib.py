@@ -87,6 +87,9 @@ SIGNATURES = {
     "teuk_orbit_circular": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int64,
                                            ctypes.POINTER(ctypes.c_double)]),
+    "teuk_orbit_eccentric": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
     "teuk_forward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P,

@@ -122,6 +122,18 @@ class Engine:
                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
+    def orbit_eccentric(self, p, e, nsamples, M=1.0, a=None, chi0=0.0):
+        """Eccentric equatorial orbit samples (nsamples, 3): semi-latus rectum
+        p, eccentricity e, anomaly chi0 at t = 0 (0 = periapsis)."""
+        info = self.info
+        if a is None:
+            raise ValueError("pass the spin a of this instance")
+        out = np.zeros((int(nsamples), 3), dtype=np.float64)
+        L.check(self._lib.teuk_orbit_eccentric(float(M), float(a), float(p), float(e), float(chi0),
+                                               float(info["dt"]), int(nsamples),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
     def set_source(self, orbit, amplitude=1.0, sigma_r_cells=2.0, sigma_th_cells=2.0,
                    cutoff_sigmas=8.0):
         if orbit is None:

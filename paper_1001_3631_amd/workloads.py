@@ -80,6 +80,40 @@ def batched_instances(seed=3, n=64):
     return out
 
 
+ADJOINT_AT_SCALE = dict(  # 16 eccentric-orbit instances on 12800 x 256, forward + checkpointed adjoint
+    name="adjoint_at_scale_16x12800x256",
+    instances=16,
+    seed=5,
+    steps=50000,
+    source=dict(amplitude=1.0, sigma_r_cells=2.0, sigma_th_cells=2.0, cutoff_sigmas=8.0),
+    # target: the same instance's waveform at source amplitude 0.9 (zero
+    # initial data, so w is linear in A and the target is 0.9 w)
+    target_amplitude=0.9,
+)
+
+
+def adjoint_at_scale_instances(seed=5, n=16):
+    """16 instances on 12800 x 256: a uniform in [0, 0.95], m uniform in
+    {2, 3}, eccentric equatorial orbits with p uniform in [8, 14] M, e
+    uniform in [0, 0.5] and anomaly at t = 0 uniform in [0, 2 pi).  cfl 0.25
+    (as for the other batches with m = 3); extraction at r* = 100M, which the
+    signal from the orbit reaches well within the run (at 50000 iterations
+    the runs span 200-310 M)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 0.95, n)
+    m = rng.integers(2, 4, n)
+    p = rng.uniform(8.0, 14.0, n)
+    e = rng.uniform(0.0, 0.5, n)
+    chi0 = rng.uniform(0.0, 2.0 * np.pi, n)
+    out = []
+    for k in range(n):
+        out.append(dict(
+            grid=dict(M=1.0, a=float(a[k]), s=-2, m=int(m[k]), nr=12800, nth=256, rs_min=-200.0,
+                      rs_max=600.0, cfl=0.25, rs_extract=100.0, ko_eps=KO_EPS),
+            orbit=dict(p=float(p[k]), e=float(e[k]), chi0=float(chi0[k]))))
+    return out
+
+
 def complex_normal(rng, shape):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 

@@ -71,3 +71,42 @@ def test_host_orbit_builder_matches_oracle(a):
     np.testing.assert_allclose(out[:, 1], ref["th"], rtol=0, atol=0)
     np.testing.assert_allclose(out[:, 2], ref["phi"], rtol=1e-14, atol=1e-300)
     assert lib.teuk_orbit_circular(1.0, a, 1.0, dt, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == L.TEUK_EINVAL
+
+
+@pytest.mark.parametrize("M,a,p,e,chi0,dt,ns", [
+    (1.0, 0.9, 10.0, 0.4, 0.7, 0.02, 300),
+    (1.0, 0.3, 8.0, 0.5, 0.0, 0.05, 300),
+    (2.0, 1.0, 20.0, 0.3, 2.0, 0.1, 200),
+    (1.0, 0.95, 14.0, 0.5, 3.0, 1.0, 300),
+])
+def test_host_eccentric_orbit_matches_oracle(M, a, p, e, chi0, dt, ns):
+    """teuk_orbit_eccentric (closed-form constants, cosine series in chi,
+    Newton inversion) vs the oracle's orbit (root-found constants, adaptive
+    quadrature from sample to sample), over several radial periods."""
+    lib = L.load()
+    n = 2 * ns + 1
+    out = np.zeros((n, 3))
+    L.check(lib.teuk_orbit_eccentric(M, a, p, e, chi0, dt, n,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    ref = T.eccentric_orbit(M, a, p, e, chi0, dt, ns)
+    np.testing.assert_allclose(out[:, 0], ref["rs"], rtol=1e-13)
+    np.testing.assert_array_equal(out[:, 1], ref["th"])
+    np.testing.assert_allclose(out[:, 2], ref["phi"], rtol=0, atol=1e-13)
+
+
+def test_host_eccentric_orbit_circular_limit_and_errors():
+    lib = L.load()
+    dt, n = 0.0177, 1001
+    out = np.zeros((n, 3))
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    L.check(lib.teuk_orbit_eccentric(1.0, 0.7, 10.0, 0.0, 0.0, dt, n, ptr))
+    ref = T.circular_orbit(1.0, 0.7, 10.0, dt, (n - 1) // 2)
+    np.testing.assert_allclose(out[:, 0], ref["rs"], rtol=1e-14)
+    np.testing.assert_allclose(out[:, 2], ref["phi"], rtol=1e-13, atol=1e-300)
+    for args in [(1.0, 0.9, 10.0, 0.95, 0.0, dt),     # e beyond the series' range
+                 (1.0, 0.0, 6.5, 0.5, 0.0, dt),       # inside the separatrix p = 6 + 2e
+                 (1.0, 1.0, 10.0, 0.2, 0.0, dt),      # |a| = M
+                 (1.0, 0.5, 10.0, 0.2, 0.0, 0.0),     # dt = 0
+                 (1.0, 0.5, 10.0, -0.1, 0.0, dt)]:
+        assert lib.teuk_orbit_eccentric(*args, n, ptr) == L.TEUK_EINVAL, args
+    assert lib.teuk_orbit_eccentric(1.0, 0.5, 10.0, 0.2, 0.0, dt, n, None) == L.TEUK_EINVAL
