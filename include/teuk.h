@@ -232,12 +232,16 @@ int teuk_check_finite(teuk_ctx* ctx);
  *             and writing u^{n+k} to HBM once; (seg_rows, k_steps) one of
  *             (4, 2), (8, 2), (4, 4).  teuk_step_n runs floor(nsteps / k)
  *             blocks and the remainder as single iterations.
+ *   adj_seg_rows  theta rows per wave segment of the adjoint kernel
+ *             (teuk_adjoint_step_n), 4, 8 or 16; 0 in teuk_set_tuning leaves
+ *             it unchanged.  Default 4 (teuk_autotune does not change it).
  * The default (k_steps 1, seg_rows from the grid size) is set by
- * teuk_init_grid; teuk_autotune chooses by measurement.  EINVAL for any
- * other pair. */
+ * teuk_init_grid; teuk_autotune chooses (seg_rows, k_steps) by measurement.
+ * EINVAL for any other values. */
 typedef struct {
     int32_t seg_rows;
     int32_t k_steps;
+    int32_t adj_seg_rows;
 } teuk_tuning;
 
 int teuk_set_tuning(teuk_ctx* ctx, const teuk_tuning* t);

@@ -45,7 +45,7 @@ class Info(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32)]
+    _fields_ = [("seg_rows", ctypes.c_int32), ("k_steps", ctypes.c_int32), ("adj_seg_rows", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):

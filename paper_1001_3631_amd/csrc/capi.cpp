@@ -185,6 +185,11 @@ int teuk_detail::ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward
 
 namespace {
 
+void set_adjoint_segment(teuk_ctx* c, int seg) {
+    c->adj_seg_rows = seg;
+    c->adj_nseg = (c->G.nth - 3) / seg + 1;
+}
+
 void set_tuning_fields(teuk_ctx* c, int seg, int k) {
     c->seg_rows = seg;
     c->k_steps = k;
@@ -225,9 +230,17 @@ int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
     c->ld = (G.nr + 15) / 16 * 16;
     c->ko_c = d->ko_eps / 16.0;
     c->nstrips = (G.nr + 61) / 62;
-    // default segment: 8 rows when that still gives at least one wave per SIMD
-    // (256 CUs x 4 SIMDs), else 4; the autotuner refines this by measurement
-    set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= 1024) ? 8 : 4, 1);
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->nsimd = 4 * cus;
+    }
+    // default segment: 8 rows when that still gives at least one wave per
+    // SIMD, else 4; the autotuner refines this by measurement.  The adjoint
+    // runs 4-row segments (fastest on every grid measured, large or small).
+    set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= c->nsimd) ? 8 : 4, 1);
+    set_adjoint_segment(c, 4);
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
     auto alloc = [&](void** p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
@@ -536,7 +549,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.ld = c->ld;
     P.rpitch = G.nr;
     P.nstrips = c->nstrips;
-    P.nseg = c->nseg;
+    P.nseg = c->adj_nseg;
     P.dt = G.dt;
     P.inv_hr = 1.0 / G.h_r;
     P.ko_c = c->ko_c;
@@ -545,7 +558,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.i_ext = G.i_ext;
     P.win_r = c->win_r;
     P.win_t = c->win_t;
-    const int items = c->nstrips * c->nseg;
+    const int items = c->nstrips * c->adj_nseg;
     if (c->part_items != items) {
         if (int rc = flush_partials(c)) return rc;
         c->part_items = items;
@@ -572,7 +585,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
         P.lam_pi = c->adj[c->adj_cur][1];
         P.out_phi = c->adj[c->adj_cur ^ 1][0];
         P.out_pi = c->adj[c->adj_cur ^ 1][1];
-        HIP_TRY(teuk::launch_adjoint(P, c->seg_rows, c->stream), "adjoint kernel");
+        HIP_TRY(teuk::launch_adjoint(P, c->adj_seg_rows, c->stream), "adjoint kernel");
         c->adj_cur ^= 1;
         c->adj_clock = m;
     }
@@ -765,7 +778,10 @@ int teuk_set_tuning(teuk_ctx* c, const teuk_tuning* t) {
     } else if (!teuk::valid_block(t->seg_rows, t->k_steps)) {
         return fail(TEUK_EINVAL, "no blocked variant for this (seg_rows, k_steps); valid: (4,2), (8,2), (4,4)");
     }
+    if (t->adj_seg_rows != 0 && !teuk::valid_segment_rows(t->adj_seg_rows))
+        return fail(TEUK_EINVAL, "adj_seg_rows must be 0, 4, 8 or 16");
     set_tuning_fields(c, t->seg_rows, t->k_steps);
+    if (t->adj_seg_rows != 0) set_adjoint_segment(c, t->adj_seg_rows);
     return TEUK_OK;
 }
 
@@ -774,6 +790,7 @@ int teuk_get_tuning(const teuk_ctx* c, teuk_tuning* out) {
     if (out == nullptr) return fail(TEUK_EINVAL, "null output");
     out->seg_rows = c->seg_rows;
     out->k_steps = c->k_steps;
+    out->adj_seg_rows = c->adj_seg_rows;
     return TEUK_OK;
 }
 

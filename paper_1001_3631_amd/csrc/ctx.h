@@ -50,6 +50,8 @@ struct teuk_ctx {
     int* d_flag = nullptr;
     double ko_c = 0.0;
     int nstrips = 0, nseg = 0, seg_rows = 16;
+    int adj_seg_rows = 4, adj_nseg = 0;   // theta rows per wave segment of the adjoint kernel
+    int nsimd = 1024;                     // SIMDs of the device (4 per compute unit)
     int k_steps = 1;               // iterations per stencil launch (temporal blocking depth)
     int bstrips = 0;               // strips of the blocked kernel at depth k_steps
     int64_t steps_done = 0;

@@ -172,11 +172,13 @@ class Engine:
     def tuning(self):
         t = L.Tuning()
         L.check(self._lib.teuk_get_tuning(self.ctx, ctypes.byref(t)))
-        return {"seg_rows": t.seg_rows, "k_steps": t.k_steps}
+        return {"seg_rows": t.seg_rows, "k_steps": t.k_steps, "adj_seg_rows": t.adj_seg_rows}
 
-    def set_tuning(self, seg_rows, k_steps=1):
-        """Launch configuration: theta rows per segment and iterations per launch."""
-        t = L.Tuning(int(seg_rows), int(k_steps))
+    def set_tuning(self, seg_rows, k_steps=1, adj_seg_rows=0):
+        """Launch configuration: theta rows per segment and iterations per
+        launch of the stepper; theta rows per segment of the adjoint (0 keeps
+        the current value)."""
+        t = L.Tuning(int(seg_rows), int(k_steps), int(adj_seg_rows))
         L.check(self._lib.teuk_set_tuning(self.ctx, ctypes.byref(t)))
 
     def autotune(self, cache_path=None):

@@ -124,7 +124,8 @@ def test_reverse_sweep_bitwise_invariant_to_segment_length(grid):
     outs = []
     for seg in (4, 8, 16):
         eng = gpu_engine(grid)
-        eng.set_tuning(seg)
+        eng.set_tuning(seg, 1, seg)
+        assert eng.tuning["adj_seg_rows"] == seg
         gpu_source(eng, grid, SRC, 6)
         eng.adjoint_begin(6, to_dev(lp), to_dev(lq), gw=gw)
         eng.adjoint_step(6)

@@ -118,3 +118,31 @@ def test_adjoint_at_scale_instance_full_size():
     assert e_dA <= 1e-10
     assert worst <= 1e-9
     eng.close()
+
+
+@pytest.mark.parametrize("adj_seg", [4, 8])
+def test_adjoint_at_scale_one_reverse_iteration_against_oracle(adj_seg):
+    """One GPU reverse iteration on 12800 x 256 (13248 or 6624 waves) with
+    the eccentric source, from a lambda made by 20 GPU reverse iterations
+    from a seeded state, against one oracle reverse iteration on the same
+    lambda: every point, including the strip seams inside the source window."""
+    cfg = W.ADJOINT_AT_SCALE
+    inst = W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])[9]
+    grid, orb = inst["grid"], inst["orbit"]
+    g = T.Grid(**grid)
+    m0 = 150
+    eng = _gpu(grid, orb, m0 + 40)
+    eng.set_tuning(8, 1, adj_seg)
+    lp, lq = W.random_state(g.nth, g.nr, seed=52)
+    eng.adjoint_begin(m0 + 20, to_dev(lp), to_dev(lq))
+    eng.adjoint_step(20)
+    p0, q0, _ = eng.adjoint_get(want_dA=False)
+    p0, q0 = host(p0), host(q0)
+    eng.adjoint_begin(m0, to_dev(p0), to_dev(q0))
+    eng.adjoint_step(1)
+    p1, q1, dA = eng.adjoint_get()
+    rp, rq, rdA = T.adjoint_step(g, p0, q0, m0 - 1, _oracle_source(g, orb, m0 + 40))
+    e = (rel(host(p1), rp), rel(host(q1), rq), abs(dA - rdA) / abs(rdA))
+    print(f"adjoint at scale, one reverse iteration, adj seg {adj_seg}: {e}")
+    assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
+    eng.close()
