@@ -74,7 +74,13 @@ __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
 
 }  // namespace
 
-template <int SEG>
+// PART selects the waves a launch runs: 0 all of them; 1 those that meet no
+// source window; 2 those that do.  A launch of part 1 carries no source
+// bodies and so fits 248 VGPRs at seg 4 (two waves per SIMD, no spills),
+// where the kernel with all four bodies takes 264 (one wave per SIMD).
+// Parts 1 and 2 together run every wave once, each through the same body
+// as part 0, so the results are the same bits.
+template <int SEG, int PART>
 __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
     // rows jlo-4 .. jhi+5 (jhi - jlo <= SEG + 2).  Output row r needs mu rows
     // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
@@ -301,14 +307,23 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                      (window_meets(org, false, P.win_r, P.win_t, i0, jlo, jhi - 1) ||
                       window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
     if (src) {   // uniform per wave
-        if (interior)
-            body(std::true_type{}, std::true_type{});
-        else
-            body(std::false_type{}, std::true_type{});
-    } else if (interior) {
-        body(std::true_type{}, std::false_type{});
+        if constexpr (PART == 1) {
+            return;
+        } else {
+            if (interior)
+                body(std::true_type{}, std::true_type{});
+            else
+                body(std::false_type{}, std::true_type{});
+        }
     } else {
-        body(std::false_type{}, std::false_type{});
+        if constexpr (PART == 2) {
+            return;
+        } else {
+            if (interior)
+                body(std::true_type{}, std::false_type{});
+            else
+                body(std::false_type{}, std::false_type{});
+        }
     }
     // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
     if (P.dA_part != nullptr) {
@@ -373,13 +388,27 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream) {
+hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream) {
     const int items = P.nstrips * P.nseg;
     const dim3 grid((items + 3) / 4), block(256);
+    // With a source on a grid of more waves than SIMDs, the waves without
+    // it run in a launch of their own at two waves per SIMD (seg 4), and the
+    // few with it in a second launch.  Smaller grids run one wave per SIMD
+    // anyway, and the second launch would only add its cost.
+    const bool split = seg == 4 && P.fh != nullptr && P.fn != nullptr && items > nsimd;
     switch (seg) {
-        case 4: hipLaunchKernelGGL(lw_adjoint_kernel<4>, grid, block, 0, stream, P, P.rows); break;
-        case 8: hipLaunchKernelGGL(lw_adjoint_kernel<8>, grid, block, 0, stream, P, P.rows); break;
-        case 16: hipLaunchKernelGGL(lw_adjoint_kernel<16>, grid, block, 0, stream, P, P.rows); break;
+        case 4:
+            if (split) {
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 2>), grid, block, 0, stream, P, P.rows);
+            } else if (P.fh != nullptr && P.fn != nullptr) {
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 0>), grid, block, 0, stream, P, P.rows);
+            } else {
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
+            }
+            break;
+        case 8: hipLaunchKernelGGL((lw_adjoint_kernel<8, 0>), grid, block, 0, stream, P, P.rows); break;
+        case 16: hipLaunchKernelGGL((lw_adjoint_kernel<16, 0>), grid, block, 0, stream, P, P.rows); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -585,7 +585,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
         P.lam_pi = c->adj[c->adj_cur][1];
         P.out_phi = c->adj[c->adj_cur ^ 1][0];
         P.out_pi = c->adj[c->adj_cur ^ 1][1];
-        HIP_TRY(teuk::launch_adjoint(P, c->adj_seg_rows, c->stream), "adjoint kernel");
+        HIP_TRY(teuk::launch_adjoint(P, c->adj_seg_rows, c->nsimd, c->stream), "adjoint kernel");
         c->adj_cur ^= 1;
         c->adj_clock = m;
     }

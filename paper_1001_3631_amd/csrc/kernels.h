@@ -125,7 +125,9 @@ hipError_t launch_add_region(double2* lam, int ld, const double2* src, int src_l
                              int i0, int i1, int j0, int j1, hipStream_t stream);
 
 bool valid_segment_rows(int seg);
-hipError_t launch_adjoint(const AdjointParams& P, int seg, hipStream_t stream);
+// nsimd: SIMDs of the device (a launch of more waves than that splits off
+// the source waves, see adjoint.hip).
+hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream);
 int reduce_partials_blocks(int n);
 hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream);
 hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream);

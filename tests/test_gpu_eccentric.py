@@ -3,7 +3,7 @@ against the oracle with its own (independently built) orbit, for the field,
 the waveform and the gradient; and the 16-instance 12800 x 256 workload's
 forward + checkpointed adjoint checked at full size through properties that
 hold at any size (dL/dA in closed form, the adjoint identity along seeded
-directions)."""
+directions; the split adjoint launch against the single one)."""
 
 import numpy as np
 import pytest
@@ -146,3 +146,27 @@ def test_adjoint_at_scale_one_reverse_iteration_against_oracle(adj_seg):
     print(f"adjoint at scale, one reverse iteration, adj seg {adj_seg}: {e}")
     assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
     eng.close()
+
+
+def test_adjoint_split_launch_bitwise_equal_to_single_launch():
+    """On 12800 x 256 with a source, adjoint segments of 4 rows run as two
+    launches (waves without the source window, then waves with it); 8 and 16
+    rows run as one.  The same reverse sweep from a seeded lambda gives the
+    same bits either way, and dL/dA to the reduction's rounding."""
+    cfg = W.ADJOINT_AT_SCALE
+    inst = W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])[9]
+    grid, orb = inst["grid"], inst["orbit"]
+    lp, lq = W.random_state(grid["nth"], grid["nr"], seed=53)
+    gw = to_dev(W.target_noise((8, grid["nth"]), 1.0, seed=54))
+    outs = []
+    for seg in (4, 8, 16):
+        eng = _gpu(grid, orb, 40)
+        eng.set_tuning(8, 1, seg)
+        eng.adjoint_begin(8, to_dev(lp), to_dev(lq), gw=gw)
+        eng.adjoint_step(8)
+        p, q, dA = eng.adjoint_get()
+        outs.append((host(p), host(q), dA))
+        eng.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+        assert abs(o[2] - outs[0][2]) <= 1e-13 * abs(outs[0][2])
