@@ -75,7 +75,8 @@ __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
 }  // namespace
 
 // PART selects the waves a launch runs: 0 all of them; 1 those that meet no
-// source window; 2 those that do.  A launch of part 1 carries no source
+// source window; 2 those that do (its grid covers only the rectangle of
+// items near the windows, P.sub_*).  A launch of part 1 carries no source
 // bodies and so fits 248 VGPRs at seg 4 (two waves per SIMD, no spills),
 // where the kernel with all four bodies takes 264 (one wave per SIMD).
 // Parts 1 and 2 together run every wave once, each through the same body
@@ -86,12 +87,20 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
     constexpr int NT = SEG + 12;
     const int lane = threadIdx.x & 63;
-    const int wg = a_xcd_remap(blockIdx.x, gridDim.x);
     // wave-uniform work item in a scalar register (row branches become scalar
     // and the angular records, a separate __restrict__ argument, are fetched
     // through the scalar cache)
-    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
-    if (item >= P.nstrips * P.nseg) return;
+    int item;
+    if constexpr (PART == 2) {   // only the rectangle of items near the source windows
+        const int local = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (local >= P.sub_ns * P.sub_ng) return;
+        const int a = local / P.sub_ng;
+        item = (P.sub_s0 + a) * P.nseg + P.sub_g0 + (local - a * P.sub_ng);
+    } else {
+        const int wg = a_xcd_remap(blockIdx.x, gridDim.x);
+        item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+        if (item >= P.nstrips * P.nseg) return;
+    }
     const int strip = item / P.nseg;
     const int seg = item - strip * P.nseg;
     const int i = strip * 62 - 1 + lane;
@@ -388,6 +397,8 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
     return hipGetLastError();
 }
 
+bool adjoint_splits(int seg, int items, int nsimd) { return seg == 4 && items > nsimd; }
+
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream) {
     const int items = P.nstrips * P.nseg;
     const dim3 grid((items + 3) / 4), block(256);
@@ -395,12 +406,15 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
     // it run in a launch of their own at two waves per SIMD (seg 4), and the
     // few with it in a second launch.  Smaller grids run one wave per SIMD
     // anyway, and the second launch would only add its cost.
-    const bool split = seg == 4 && P.fh != nullptr && P.fn != nullptr && items > nsimd;
+    const bool split = P.fh != nullptr && P.fn != nullptr && adjoint_splits(seg, items, nsimd);
     switch (seg) {
         case 4:
             if (split) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
-                hipLaunchKernelGGL((lw_adjoint_kernel<4, 2>), grid, block, 0, stream, P, P.rows);
+                const int sub = P.sub_ns * P.sub_ng;
+                if (sub > 0)
+                    hipLaunchKernelGGL((lw_adjoint_kernel<4, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
+                                       P.rows);
             } else if (P.fh != nullptr && P.fn != nullptr) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 0>), grid, block, 0, stream, P, P.rows);
             } else {

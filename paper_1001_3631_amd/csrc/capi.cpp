@@ -60,6 +60,7 @@ void free_source(teuk_ctx* c) {
     c->d_orbit = nullptr;
     c->d_fh = c->d_fn = nullptr;
     c->d_org = nullptr;
+    c->h_orbit.clear();
     c->has_src = false;
     c->batch_n0 = -1;
     c->batch_len = 0;
@@ -196,6 +197,45 @@ void set_tuning_fields(teuk_ctx* c, int seg, int k) {
     c->nseg = (c->G.nth - 3) / seg + 1;
     const int w = teuk::block_strip_width(k);
     c->bstrips = (c->G.nr + w - 1) / w;
+}
+
+// The adjoint's work items (strip x segment) whose output rows and columns
+// may meet the source windows of forward iteration m.  The origins are
+// computed as the source pass computes them, from the host's copy of the
+// same orbit samples, and widened by 2 cells against any difference in
+// rounding; the kernel still tests every wave itself.  ns or ng is 0 when
+// no item can meet them.
+void source_items(const teuk_ctx* c, int64_t m, int seg_rows, int nseg, int& s0, int& ns, int& g0, int& ng) {
+    const Geometry& G = c->G;
+    const double* sh = c->h_orbit.data() + 3 * static_cast<size_t>(2 * m);
+    const double* sn = c->h_orbit.data() + 3 * static_cast<size_t>(2 * m + 1);
+    const double Rr = c->cut * c->sig_r, Rt = c->cut * c->sig_th;
+    auto idx = [](double v) { return static_cast<int>(std::fmin(std::fmax(std::floor(v), -1e8), 1e8)); };
+    const int cx = idx((sh[0] - Rr - (G.rs_min + 0.5 * G.h_r)) / G.h_r);
+    const int ry = idx((sh[1] - Rt) / G.h_th);
+    const int cz = idx((sn[0] - Rr - G.rs_min) / G.h_r);
+    const int rw = idx((sn[1] - Rt) / G.h_th);
+    const int c_lo = std::min(cx, cz) - 2, c_hi = std::max(cx, cz) + c->win_r + 2;   // columns [c_lo, c_hi)
+    const int r_lo = std::min(ry, rw) - 2, r_hi = std::max(ry, rw) + c->win_t + 2;   // rows [r_lo, r_hi)
+    int slo = -1, shi = -1, glo = -1, ghi = -1;
+    for (int s = 0; s < c->nstrips; ++s) {
+        const int i0 = 62 * s - 1;   // the wave's 64 columns i0 .. i0 + 63
+        if (c_lo <= i0 + 63 && i0 < c_hi) {
+            if (slo < 0) slo = s;
+            shi = s;
+        }
+    }
+    for (int g = 0; g < nseg; ++g) {
+        const int jlo = g * seg_rows, jhi = (g == nseg - 1) ? G.nth : jlo + seg_rows;
+        if (r_lo <= jhi - 1 && jlo < r_hi) {
+            if (glo < 0) glo = g;
+            ghi = g;
+        }
+    }
+    s0 = std::max(slo, 0);
+    g0 = std::max(glo, 0);
+    ns = slo < 0 ? 0 : shi - slo + 1;
+    ng = glo < 0 ? 0 : ghi - glo + 1;
 }
 
 int flush_partials(teuk_ctx* c) {
@@ -388,6 +428,7 @@ int teuk_set_source(teuk_ctx* c, const teuk_source_desc* s) {
     if (e == hipSuccess) e = hipMalloc(&c->d_fn, tbytes);
     if (e == hipSuccess) e = hipMalloc(&c->d_org, sizeof(int4) * kSourceBatch);
     if (e == hipSuccess) e = hipMemcpy(c->d_orbit, s->orbit, obytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) c->h_orbit.assign(s->orbit, s->orbit + 3 * static_cast<size_t>(s->nsamples));
     if (e != hipSuccess) {
         free_source(c);
         return hip_fail(e, "set_source");
@@ -558,6 +599,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.i_ext = G.i_ext;
     P.win_r = c->win_r;
     P.win_t = c->win_t;
+    P.sub_s0 = P.sub_ns = P.sub_g0 = P.sub_ng = 0;
     const int items = c->nstrips * c->adj_nseg;
     if (c->part_items != items) {
         if (int rc = flush_partials(c)) return rc;
@@ -575,6 +617,8 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
             P.org = c->d_org + slot;
+            if (teuk::adjoint_splits(c->adj_seg_rows, items, c->nsimd))
+                source_items(c, m, c->adj_seg_rows, c->adj_nseg, P.sub_s0, P.sub_ns, P.sub_g0, P.sub_ng);
             if (c->part_filled == kPartSteps)
                 if (int rc = flush_partials(c)) return rc;
             P.dA_part = c->d_dA_part + static_cast<size_t>(c->part_filled) * items;

@@ -60,6 +60,7 @@ struct teuk_ctx {
     double amplitude = 0.0, sig_r = 0.0, sig_th = 0.0, cut = 0.0;
     int64_t nsamples = 0;
     double* d_orbit = nullptr;
+    std::vector<double> h_orbit;   // host copy of the orbit (3 per sample)
     int win_r = 0, win_t = 0;
     double2* d_fh = nullptr;
     double2* d_fn = nullptr;

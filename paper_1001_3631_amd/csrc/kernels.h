@@ -117,6 +117,11 @@ struct AdjointParams {
     const int4* org;
     int win_r, win_t;
     double* dA_part;            // one partial of dL/dA per wave (nstrips * nseg), or null
+    // the work items that may meet the source windows: strips [sub_s0,
+    // sub_s0 + sub_ns) x segments [sub_g0, sub_g0 + sub_ng) (a superset,
+    // from the host's copy of the orbit); the source waves' launch covers
+    // only these
+    int sub_s0, sub_ns, sub_g0, sub_ng;
 };
 
 hipError_t launch_region_sumsq(const double2* phi, int ld, int i0, int i1, int j0, int j1, double* part,
@@ -128,6 +133,9 @@ bool valid_segment_rows(int seg);
 // nsimd: SIMDs of the device (a launch of more waves than that splits off
 // the source waves, see adjoint.hip).
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream);
+// Whether launch_adjoint runs the waves near the source windows in a launch
+// of their own (then it reads P.sub_*).
+bool adjoint_splits(int seg, int items, int nsimd);
 int reduce_partials_blocks(int n);
 hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream);
 hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream);
