@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
 
     int4 org = make_int4(0, 0, 0, 0);
     if (P.org != nullptr) org = *P.org;
-    const RCol rn = load_rcol(P.rnode, P.rpitch, min(max(i, 0), P.nr - 1));
-    const RCol rh = load_rcol(P.rhalf, P.rpitch, min(max(i, 0), P.nr - 2));
+    const RCol rn = load_rcol(P.rnode, P.nr, min(max(i, 0), P.nr - 1));
+    const RCol rh = load_rcol(P.rhalf, P.nr, min(max(i, 0), P.nr - 2));
 
     double dA = 0.0;
 
@@ -397,7 +397,9 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
     return hipGetLastError();
 }
 
-bool adjoint_splits(int seg, int items, int nsimd) { return seg == 4 && items > nsimd; }
+bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
+    return seg == 4 && nstrips * nseg > nsimd && nstrips <= INT16_MAX && nseg <= INT16_MAX;
+}
 
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream) {
     const int items = P.nstrips * P.nseg;
@@ -406,7 +408,7 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
     // it run in a launch of their own at two waves per SIMD (seg 4), and the
     // few with it in a second launch.  Smaller grids run one wave per SIMD
     // anyway, and the second launch would only add its cost.
-    const bool split = P.fh != nullptr && P.fn != nullptr && adjoint_splits(seg, items, nsimd);
+    const bool split = P.fh != nullptr && P.fn != nullptr && adjoint_splits(seg, P.nstrips, P.nseg, nsimd);
     switch (seg) {
         case 4:
             if (split) {

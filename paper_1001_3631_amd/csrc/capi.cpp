@@ -588,7 +588,6 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.nr = G.nr;
     P.nth = G.nth;
     P.ld = c->ld;
-    P.rpitch = G.nr;
     P.nstrips = c->nstrips;
     P.nseg = c->adj_nseg;
     P.dt = G.dt;
@@ -617,8 +616,14 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
             P.org = c->d_org + slot;
-            if (teuk::adjoint_splits(c->adj_seg_rows, items, c->nsimd))
-                source_items(c, m, c->adj_seg_rows, c->adj_nseg, P.sub_s0, P.sub_ns, P.sub_g0, P.sub_ng);
+            if (teuk::adjoint_splits(c->adj_seg_rows, c->nstrips, c->adj_nseg, c->nsimd)) {
+                int s0, ns, g0, ng;
+                source_items(c, m, c->adj_seg_rows, c->adj_nseg, s0, ns, g0, ng);
+                P.sub_s0 = static_cast<int16_t>(s0);
+                P.sub_ns = static_cast<int16_t>(ns);
+                P.sub_g0 = static_cast<int16_t>(g0);
+                P.sub_ng = static_cast<int16_t>(ng);
+            }
             if (c->part_filled == kPartSteps)
                 if (int rc = flush_partials(c)) return rc;
             P.dA_part = c->d_dA_part + static_cast<size_t>(c->part_filled) * items;

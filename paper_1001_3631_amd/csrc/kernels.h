@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "geometry.h"
 
 namespace teuk {
@@ -99,29 +101,31 @@ struct PulseParams {
 };
 
 struct AdjointParams {
+    // (ordered for a compact argument block: every launch copies it, and a
+    // larger block cost 0.2 us per launch on small grids)
     const double2* lam_phi;     // lambda^{n+1} planes [nth][ld]
     const double2* lam_pi;
     double2* out_phi;           // lambda^n planes
     double2* out_pi;
-    const double* rnode;
+    const double* rnode;        // radial records, pitch nr
     const double* rhalf;
     const ThetaRow* rows;
-    int nr, nth, ld, rpitch;
+    int nr, nth, ld;
     int nstrips, nseg;
-    double dt, inv_hr, ko_c;
-    int even, kerr;
     int i_ext;
+    double dt, inv_hr, ko_c;
     const double2* gw;          // dL/dw_n to inject at column i_ext after the step (nth), or null
     const double2* fh;          // unit-amplitude source windows of the forward iteration n
     const double2* fn;
     const int4* org;
-    int win_r, win_t;
     double* dA_part;            // one partial of dL/dA per wave (nstrips * nseg), or null
+    int win_r, win_t;
     // the work items that may meet the source windows: strips [sub_s0,
     // sub_s0 + sub_ns) x segments [sub_g0, sub_g0 + sub_ng) (a superset,
     // from the host's copy of the orbit); the source waves' launch covers
     // only these
-    int sub_s0, sub_ns, sub_g0, sub_ng;
+    int16_t sub_s0, sub_ns, sub_g0, sub_ng;
+    uint8_t even, kerr;
 };
 
 hipError_t launch_region_sumsq(const double2* phi, int ld, int i0, int i1, int j0, int j1, double* part,
@@ -135,7 +139,8 @@ bool valid_segment_rows(int seg);
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream);
 // Whether launch_adjoint runs the waves near the source windows in a launch
 // of their own (then it reads P.sub_*).
-bool adjoint_splits(int seg, int items, int nsimd);
+// (the rectangle of source items is held in 16-bit fields, hence the limits)
+bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd);
 int reduce_partials_blocks(int n);
 hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream);
 hipError_t launch_inject_column(double2* phi, int ld, int nth, int col, const double2* g, hipStream_t stream);
