@@ -188,6 +188,7 @@ def adjoint_at_scale(args):
     pts = 0
     worst_dA = 0.0
     snap_bytes = peak_used = 0
+    w2_max = 0.0
     tuning = None
     for k, inst in enumerate(W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])):
         g, o = inst["grid"], inst["orbit"]
@@ -214,7 +215,9 @@ def adjoint_at_scale(args):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         eng.check_finite()
-        ref = 2.0 * (1.0 - cfg["target_amplitude"]) * float(torch.sum(torch.abs(w) ** 2))
+        w2 = float(torch.sum(torch.abs(w) ** 2))
+        w2_max = max(w2_max, w2)
+        ref = 2.0 * (1.0 - cfg["target_amplitude"]) * w2
         worst_dA = max(worst_dA, abs(dA - ref) / max(abs(ref), 1e-300))
         tf += t1 - t0
         tb += t2 - t1
@@ -233,7 +236,10 @@ def adjoint_at_scale(args):
             "forward_gpts": round(pts / tf / 1e9, 3),
             "snapshot_bytes_per_instance": int(snap_bytes),
             "device_bytes_used_per_instance": int(peak_used),
-            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}")}
+            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}"),
+            # 0 means no signal reached the extraction radius in this many
+            # iterations (then the dL/dA check above is empty)
+            "waveform_norm2_max": float(f"{w2_max:.6e}")}
 
 
 def batched(args):
