@@ -341,3 +341,19 @@ def test_adjoint_fullsize_gradient_vs_central_differences_32_directions():
         worst = max(worst, abs(fd - ad) / max(abs(ad), 1e-300))
     print("adjoint_3200x64: worst relative |FD - adjoint| over 32 directions:", worst)
     assert worst <= 1e-6
+
+
+def test_adjoint_segment_setting():
+    """teuk_tuning.adj_seg_rows: default 4, 0 keeps the current value, the
+    stepper's own settings do not touch it, invalid values are refused."""
+    from paper_1001_3631_amd import _lib as L
+    eng = gpu_engine(STEP_GRIDS[0])
+    assert eng.tuning["adj_seg_rows"] == 4
+    eng.set_tuning(8, 1, 16)
+    assert eng.tuning == {"seg_rows": 8, "k_steps": 1, "adj_seg_rows": 16}
+    eng.set_tuning(4, 2)
+    assert eng.tuning == {"seg_rows": 4, "k_steps": 2, "adj_seg_rows": 16}
+    with pytest.raises(L.TeukError):
+        eng.set_tuning(8, 1, 5)
+    assert eng.tuning == {"seg_rows": 4, "k_steps": 2, "adj_seg_rows": 16}
+    eng.close()
