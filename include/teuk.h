@@ -30,9 +30,16 @@
  *   - Work is enqueued on the stream given to teuk_init_grid and runs
  *     asynchronously; calls that return host data synchronize that stream.
  *   - A context is not thread safe; use one context per host thread.
- *   - The library allocates its own device memory for the state (two time
- *     levels), the coefficient tables, the orbit and the source windows; it is
- *     released by teuk_destroy.
+ *   - Device memory belongs to the caller.  A context lives in one
+ *     caller-owned device workspace (teuk_workspace_size gives its size):
+ *     the state (two time levels), the coefficient records, the source
+ *     windows and, if requested, the adjoint's planes and partial sums.  The
+ *     orbit table of a source and the snapshots of a checkpointed gradient go
+ *     into further caller-owned device buffers named at those calls.  The
+ *     library calls no device allocator; a buffer too small for what is asked
+ *     of it is TEUK_ENOMEM, reported before any work is enqueued.  Every
+ *     buffer must stay alive, unmoved, for as long as the context uses it
+ *     (the workspace: until teuk_destroy).
  */
 #ifndef TEUK_H
 #define TEUK_H
@@ -48,7 +55,7 @@ extern "C" {
 #define TEUK_EINVAL     -1   /* invalid argument or descriptor            */
 #define TEUK_EDEVICE    -2   /* HIP runtime error (message appended)      */
 #define TEUK_ENONFINITE -3   /* non-finite values found by teuk_check_finite */
-#define TEUK_ENOMEM     -4   /* device or host allocation failed          */
+#define TEUK_ENOMEM     -4   /* a caller buffer is too small, or host memory ran out */
 #define TEUK_ESTATE     -5   /* call order violated (e.g. no source set)  */
 
 typedef struct teuk_ctx teuk_ctx;
@@ -89,23 +96,52 @@ typedef struct {
  *   * exp(-i m phi~_p(t)),  G(x; s) = exp(-x^2/2s^2)/(sqrt(2 pi) s), zero where
  *   |x| > cutoff_sigmas * s.  The orbit is sampled at t_k = k dt/2,
  *   k = 0..nsamples-1: orbit[3k+0] = r*_p, orbit[3k+1] = theta_p,
- *   orbit[3k+2] = phi~_p (host array, copied at the call).  Iteration n uses
+ *   orbit[3k+2] = phi~_p (host array, read at the call).  Iteration n uses
  *   sample 2n in its half step (lw1, time t_n) and 2n+1 in its full step
- *   (lw2, time t_n + dt/2); stepping past the last sample is TEUK_ESTATE. */
+ *   (lw2, time t_n + dt/2); stepping past the last sample is TEUK_ESTATE.
+ *   orbit_dev: caller-owned device buffer of at least 3*nsamples doubles;
+ *   teuk_set_source copies the orbit into it, and the source pass reads it
+ *   there for as long as the source stays attached. */
 typedef struct {
     double amplitude;
     double sigma_r_cells, sigma_th_cells, cutoff_sigmas;
     int64_t nsamples;
     const double* orbit;
+    void* orbit_dev;
 } teuk_source_desc;
 
-/* Create a context: validate the descriptor, invert r*(r) (Newton on ln(r - r_+)),
- * build the radial and angular coefficient tables of the first-order system
- * on the host, copy them to the device and zero the state.  hip_stream is a
- * hipStream_t (NULL = the null stream).  Synchronizes. */
-int teuk_init_grid(const teuk_grid_desc* desc, void* hip_stream, teuk_ctx** out);
+/* What a context's workspace must hold besides the state and the
+ * coefficient records.
+ *   sigma_r_cells, sigma_th_cells, cutoff_sigmas  the largest source
+ *        footprint the context will be given (teuk_source_desc); the source
+ *        windows are sized for it.  All 0: no source.
+ *   adjoint  nonzero: room for the reverse sweep (teuk_adjoint_*, and the
+ *        checkpointed gradient): two more time levels and the dL/dA partial
+ *        sums.
+ * A NULL request means no source and no adjoint. */
+typedef struct {
+    double sigma_r_cells, sigma_th_cells, cutoff_sigmas;
+    int32_t adjoint;
+} teuk_ws_request;
 
-/* Release the context and all library-owned device memory.  NULL is a no-op. */
+/* Bytes of device workspace a context for (desc, req) needs (host output).
+ * Validates the descriptor as teuk_init_grid does; touches no device. */
+int teuk_workspace_size(const teuk_grid_desc* desc, const teuk_ws_request* req, size_t* bytes);
+
+/* Create a context in the caller's workspace: validate the descriptor,
+ * invert r*(r) (Newton on ln(r - r_+)), build the radial and angular
+ * coefficient records of the first-order system on the host, copy them into
+ * the workspace and zero the state.  dev_workspace: device memory of
+ * ws_bytes bytes, 256-byte aligned (TEUK_EINVAL otherwise), at least
+ * teuk_workspace_size bytes (TEUK_ENOMEM otherwise), owned by the caller and
+ * kept alive until teuk_destroy.  hip_stream is a hipStream_t (NULL = the
+ * null stream).  Synchronizes. */
+int teuk_init_grid(const teuk_grid_desc* desc, const teuk_ws_request* req, void* hip_stream,
+                   void* dev_workspace, size_t ws_bytes, teuk_ctx** out);
+
+/* Release the context (host state and events); the workspace and every other
+ * caller buffer stay with the caller.  Synchronizes the stream.  NULL is a
+ * no-op. */
 int teuk_destroy(teuk_ctx* ctx);
 
 int teuk_get_info(const teuk_ctx* ctx, teuk_info* out);
@@ -123,7 +159,9 @@ int teuk_get_state(const teuk_ctx* ctx, void* phi_dev, void* pi_dev);
  * boundary conditions.  Resets steps_done and the source clock. */
 int teuk_init_pulse(teuk_ctx* ctx, double center, double width, double amplitude);
 
-/* Attach (or with NULL detach) the synthetic source.  Copies the orbit. */
+/* Attach (or with NULL detach) the synthetic source.  Copies the orbit into
+ * src->orbit_dev (TEUK_EINVAL if NULL) and keeps a host copy.  TEUK_ENOMEM if
+ * the footprint is larger than the workspace was sized for (teuk_ws_request). */
 int teuk_set_source(teuk_ctx* ctx, const teuk_source_desc* src);
 
 /* Change the source amplitude without re-uploading the orbit. */
@@ -190,7 +228,17 @@ int teuk_adjoint_get(teuk_ctx* ctx, void* lam_phi_dev, void* lam_pi_dev, double*
  * snapshot before sweeping it in reverse (memory: nsteps/interval
  * snapshots plus one segment of the rectangle).  With state_weight = 0 the
  * states are not needed; force_recompute != 0 recomputes the segments
- * anyway (same gradient, bitwise).
+ * anyway (same gradient, bitwise).  The iteration is linear, so its reverse
+ * sweep needs no forward state, only the loss's own terms: one forward
+ * recompute in all, whatever the interval, and the interval only trades
+ * snapshot memory (nsteps/interval planes) against the rectangle buffer
+ * (interval slots).
+ *
+ * The snapshots, the rectangle buffer and the loss's partial sums live in
+ * the caller-owned device buffer ckpt_dev of ckpt_bytes bytes, 256-byte
+ * aligned, at least teuk_checkpoint_size(plan) (TEUK_ENOMEM otherwise); it
+ * must stay alive from the forward through the backward.  The context's
+ * workspace must have the adjoint area (teuk_ws_request.adjoint).
  *
  * teuk_forward_checkpointed: from the state set by teuk_set_state or
  *   teuk_init_pulse (no iteration taken since), runs plan->nsteps
@@ -209,7 +257,13 @@ typedef struct {
     int32_t i0, i1, j0, j1;
     int64_t n_lo, n_hi;
     int32_t force_recompute;
+    void* ckpt_dev;
+    uint64_t ckpt_bytes;
 } teuk_grad_plan;
+
+/* Bytes of checkpoint buffer (plan->ckpt_dev) the plan needs (host output);
+ * ckpt_dev and ckpt_bytes are not read. */
+int teuk_checkpoint_size(const teuk_ctx* ctx, const teuk_grad_plan* plan, size_t* bytes);
 
 int teuk_forward_checkpointed(teuk_ctx* ctx, const teuk_grad_plan* plan, void* waveform_dev,
                               double* state_loss);
@@ -252,8 +306,8 @@ int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
  * events (warm-up, then the best of three timed runs of a fixed number of
  * iterations, without source or extraction), keeps the fastest as the
  * context's tuning, and leaves the state, iteration count and source batch
- * as they were (the state is saved to and restored from temporary device
- * planes, allocated and freed inside the call; synchronizes the stream).
+ * as they were (the state is saved to and restored from host memory;
+ * synchronizes the stream).
  *   cache_path  host string or NULL.  A text file of lines
  *               "<key>\t<seg_rows>\t<k_steps>\t<us per iteration>", where the
  *               key names the device architecture, nr, nth, whether a != 0
@@ -265,7 +319,7 @@ int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
  *   table       host array of capacity entries or NULL: receives every
  *               measured pair (or the one cached pair), fastest first;
  *               *count (host, may be NULL) = entries written.
- * ENOMEM if the temporary planes cannot be allocated. */
+ * ENOMEM if the host copy of the state cannot be allocated. */
 typedef struct {
     int32_t seg_rows;
     int32_t k_steps;
@@ -295,9 +349,18 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  * Every point is evaluated by the same device code as teuk_step_n, so an
  * instance's results are bitwise equal to stepping it alone, in both modes.
  *
+ * teuk_batch_workspace_size: bytes of device workspace for a batch of n
+ *   instances (host output): the batch's own tables (instance table, tiles,
+ *   item offsets, completion counters, work counter, abort flag) followed by
+ *   one context workspace per instance, every instance with request req
+ *   (NULL: no source, no adjoint).  Touches no device.
  * teuk_batch_create: n >= 1 descriptors (host array); every instance gets a
- *   context as from teuk_init_grid on hip_stream (validation as there; the
- *   message names the failing instance).  Synchronizes.
+ *   context as from teuk_init_grid on hip_stream, in its part of the
+ *   caller's workspace (dev_workspace, ws_bytes: 256-byte aligned, at least
+ *   teuk_batch_workspace_size; kept alive until teuk_batch_destroy).
+ *   Validation as there; the message names the failing instance.  The
+ *   instance tables are staged through two small pinned host buffers.
+ *   Synchronizes.
  * teuk_batch_instance: borrowed context of instance k (0 <= k < n), for
  *   teuk_set_state / teuk_init_pulse / teuk_get_state / teuk_step_n / ...;
  *   teuk_destroy refuses it (EINVAL), teuk_batch_destroy frees it.
@@ -330,7 +393,9 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  *   = architecture, the instance shapes and the kernel sources. */
 typedef struct teuk_batch teuk_batch;
 
-int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, teuk_batch** out);
+int teuk_batch_workspace_size(int32_t n, const teuk_grid_desc* descs, const teuk_ws_request* req, size_t* bytes);
+int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, const teuk_ws_request* req, void* hip_stream,
+                      void* dev_workspace, size_t ws_bytes, teuk_batch** out);
 int teuk_batch_destroy(teuk_batch* batch);
 int teuk_batch_instance(teuk_batch* batch, int32_t k, teuk_ctx** out);
 int teuk_batch_set_tuning(teuk_batch* batch, int32_t seg_rows);
@@ -339,6 +404,22 @@ int teuk_batch_set_mode(teuk_batch* batch, int32_t mode);
 int teuk_batch_get_mode(const teuk_batch* batch, int32_t* mode);
 int teuk_batch_step_n(teuk_batch* batch, int64_t nsteps, void* const* waveforms);
 int teuk_batch_sync(teuk_batch* batch);
+
+/* Bounded waits of the persistent mode.
+ * teuk_batch_set_wait_limit: device wall-clock time a dependency wait may
+ *   take before the launch gives up (sets the abort flag; every wave then
+ *   leaves at the top of its next pass), 0 <= seconds <= 3600, default 2.
+ *   Synchronizes; drops the captured graphs (the limit is a launch
+ *   argument).  0 makes every wait that is not satisfied at its first check
+ *   give up.
+ * teuk_batch_abort: enqueues on the batch's stream a store of the abort
+ *   flag, so that persistent launches queued after it exit at their first
+ *   pass (per-iteration launches do not look at it).  teuk_batch_sync then
+ *   reports TEUK_EDEVICE once and clears the flag.  For cancelling queued
+ *   persistent work, and for testing the abort path without a broken
+ *   dependency. */
+int teuk_batch_set_wait_limit(teuk_batch* batch, double seconds);
+int teuk_batch_abort(teuk_batch* batch);
 int teuk_batch_autotune(teuk_batch* batch, const char* cache_path, teuk_tune_entry* table, int32_t capacity,
                         int32_t* count);
 

@@ -61,14 +61,21 @@ BATCH_PER_ITERATION = 1
 class SourceDesc(ctypes.Structure):
     _fields_ = [("amplitude", ctypes.c_double), ("sigma_r_cells", ctypes.c_double),
                 ("sigma_th_cells", ctypes.c_double), ("cutoff_sigmas", ctypes.c_double),
-                ("nsamples", ctypes.c_int64), ("orbit", ctypes.POINTER(ctypes.c_double))]
+                ("nsamples", ctypes.c_int64), ("orbit", ctypes.POINTER(ctypes.c_double)),
+                ("orbit_dev", ctypes.c_void_p)]
+
+
+class WsRequest(ctypes.Structure):
+    _fields_ = [("sigma_r_cells", ctypes.c_double), ("sigma_th_cells", ctypes.c_double),
+                ("cutoff_sigmas", ctypes.c_double), ("adjoint", ctypes.c_int32)]
 
 
 class GradPlan(ctypes.Structure):
     _fields_ = [("nsteps", ctypes.c_int64), ("interval", ctypes.c_int64),
                 ("state_weight", ctypes.c_double),
                 ("i0", ctypes.c_int32), ("i1", ctypes.c_int32), ("j0", ctypes.c_int32), ("j1", ctypes.c_int32),
-                ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64), ("force_recompute", ctypes.c_int32)]
+                ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64), ("force_recompute", ctypes.c_int32),
+                ("ckpt_dev", ctypes.c_void_p), ("ckpt_bytes", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -76,7 +83,10 @@ _CTX = ctypes.c_void_p
 
 # name -> (restype, argtypes); the exported symbol set of include/teuk.h
 SIGNATURES = {
-    "teuk_init_grid": (ctypes.c_int, [ctypes.POINTER(GridDesc), _P, ctypes.POINTER(_CTX)]),
+    "teuk_workspace_size": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(WsRequest),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "teuk_init_grid": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(WsRequest), _P, _P,
+                                      ctypes.c_size_t, ctypes.POINTER(_CTX)]),
     "teuk_destroy": (ctypes.c_int, [_CTX]),
     "teuk_get_info": (ctypes.c_int, [_CTX, ctypes.POINTER(Info)]),
     "teuk_set_state": (ctypes.c_int, [_CTX, _P, _P]),
@@ -92,6 +102,7 @@ SIGNATURES = {
                                             ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
+    "teuk_checkpoint_size": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), ctypes.POINTER(ctypes.c_size_t)]),
     "teuk_forward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P,
                                                  ctypes.POINTER(ctypes.c_double)]),
     "teuk_backward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P, ctypes.c_double, _P, _P,
@@ -105,7 +116,10 @@ SIGNATURES = {
     "teuk_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(Tuning)]),
     "teuk_autotune": (ctypes.c_int, [_CTX, ctypes.c_char_p, ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)]),
-    "teuk_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GridDesc), _P, ctypes.POINTER(_CTX)]),
+    "teuk_batch_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GridDesc),
+                                                 ctypes.POINTER(WsRequest), ctypes.POINTER(ctypes.c_size_t)]),
+    "teuk_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(GridDesc), ctypes.POINTER(WsRequest), _P,
+                                         _P, ctypes.c_size_t, ctypes.POINTER(_CTX)]),
     "teuk_batch_destroy": (ctypes.c_int, [_CTX]),
     "teuk_batch_instance": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(_CTX)]),
     "teuk_batch_set_tuning": (ctypes.c_int, [_CTX, ctypes.c_int32]),
@@ -114,6 +128,8 @@ SIGNATURES = {
     "teuk_batch_get_mode": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
     "teuk_batch_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, ctypes.POINTER(_P)]),
     "teuk_batch_sync": (ctypes.c_int, [_CTX]),
+    "teuk_batch_set_wait_limit": (ctypes.c_int, [_CTX, ctypes.c_double]),
+    "teuk_batch_abort": (ctypes.c_int, [_CTX]),
     "teuk_batch_autotune": (ctypes.c_int, [_CTX, ctypes.c_char_p, ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
     "teuk_set_kernel_timing": (ctypes.c_int, [_CTX, ctypes.c_int]),

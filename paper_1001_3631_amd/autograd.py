@@ -63,11 +63,16 @@ class TeukEvolveCheckpointed(torch.autograd.Function):
             engine.set_amplitude(float(amplitude))
         w, ls = engine.forward_checkpointed(int(nsteps), interval, state_loss)
         ctx.engine = engine
+        # the engine keeps the snapshots of its latest forward only
+        ctx.generation = engine.checkpoint_generation
         return w, torch.tensor(ls, dtype=torch.float64, device=w.device)
 
     @staticmethod
     def backward(ctx, gw, gls):
         eng = ctx.engine
+        if ctx.generation != eng.checkpoint_generation:
+            raise RuntimeError("the engine ran another checkpointed forward since this one: its snapshots "
+                               "are gone; use one engine per checkpointed evolution in a graph")
         gw = gw.detach().contiguous() if gw is not None else None
         dls = float(gls) if gls is not None else 0.0
         gp, gq, dA = eng.backward_checkpointed(gw, dls)

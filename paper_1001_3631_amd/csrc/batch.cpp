@@ -51,6 +51,7 @@ struct teuk_batch {
     int waves = 0;                      // persistent waves per launch
     int resident_waves = 0;             // 8 per CU (two per SIMD at the kernel's register use)
     long long wait_limit = 0;
+    int wall_khz = 1;                   // device wall clock rate (kHz) the wait limit is counted in
     teuk::BatchInstance* h_inst[2] = {nullptr, nullptr};   // pinned, alternate calls
     hipEvent_t h_inst_free[2] = {nullptr, nullptr};        // copy out of h_inst[k] finished
     int slot = 0;
@@ -89,14 +90,50 @@ void free_batch(teuk_batch* b) {
         if (b->h_inst[k]) (void)hipHostFree(b->h_inst[k]);
         if (b->h_inst_free[k]) (void)hipEventDestroy(b->h_inst_free[k]);
     }
-    (void)hipFree(b->d_inst);
-    (void)hipFree(b->d_tiles);
-    (void)hipFree(b->d_item0);
-    (void)hipFree(b->d_done);
-    (void)hipFree(b->d_ticket);
-    (void)hipFree(b->d_abort);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    delete b;
+    delete b;   // the device tables are the caller's workspace
+}
+
+// Byte offsets of the batch's own tables at the start of its workspace; the
+// instances' workspaces follow from `first`, each `inst[k]` bytes long.
+struct BatchLayout {
+    size_t d_inst = 0, d_tiles = 0, d_item0 = 0, d_done = 0, d_ticket = 0, d_abort = 0, first = 0, total = 0;
+    std::vector<size_t> inst;
+};
+
+std::string batch_layout(int32_t n, const teuk_grid_desc* descs, const teuk_ws_request* req, BatchLayout* L) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    long tiles = 0;
+    L->inst.assign(static_cast<size_t>(n), 0);
+    std::vector<size_t> sizes;
+    for (int32_t k = 0; k < n; ++k) {
+        const teuk_grid_desc* d = &descs[k];
+        if (!(d->ko_eps >= 0.0 && d->ko_eps <= 1.0)) return "instance " + std::to_string(k) + ": need 0 <= ko_eps <= 1";
+        teuk::Geometry G;
+        std::string err = teuk::build_geometry(d->M, d->a, d->s, d->m, d->nr, d->nth, d->rs_min, d->rs_max, d->cfl,
+                                               d->rs_extract, G);
+        teuk_detail::WsLayout W;
+        if (err.empty()) err = teuk_detail::ws_layout(G, (G.nr + 15) / 16 * 16, req, &W);
+        if (!err.empty()) return "instance " + std::to_string(k) + ": " + err;
+        L->inst[k] = W.total;
+        tiles += (G.nr + 61) / 62;
+        if (tiles > INT_MAX / 2) return "too many tiles in one batch";
+    }
+    L->d_inst = take(sizeof(teuk::BatchInstance) * static_cast<size_t>(n));
+    L->d_tiles = take(sizeof(int4) * static_cast<size_t>(tiles));
+    L->d_item0 = take(sizeof(int) * (static_cast<size_t>(n) + 1));
+    L->d_done = take(sizeof(int) * static_cast<size_t>(tiles));
+    L->d_ticket = take(sizeof(unsigned long long));
+    L->d_abort = take(sizeof(int));
+    L->first = off;
+    for (size_t w : L->inst) take(w);
+    L->total = off;
+    return "";
 }
 
 // Theta segments per strip at segment length seg (the last takes up to
@@ -243,20 +280,43 @@ int check_batch(const teuk_batch* b) {
 
 extern "C" {
 
-int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, teuk_batch** out) {
+int teuk_batch_workspace_size(int32_t n, const teuk_grid_desc* descs, const teuk_ws_request* req, size_t* bytes) {
+    if (bytes == nullptr || descs == nullptr) return fail(TEUK_EINVAL, "null descriptors or output");
+    *bytes = 0;
+    if (n < 1) return fail(TEUK_EINVAL, "a batch needs at least one instance");
+    BatchLayout L;
+    const std::string err = batch_layout(n, descs, req, &L);
+    if (!err.empty()) return fail(TEUK_EINVAL, err);
+    *bytes = L.total;
+    return TEUK_OK;
+}
+
+int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, const teuk_ws_request* req, void* hip_stream,
+                      void* ws, size_t ws_bytes, teuk_batch** out) {
     if (out == nullptr || descs == nullptr) return fail(TEUK_EINVAL, "null descriptors or output");
     *out = nullptr;
     if (n < 1) return fail(TEUK_EINVAL, "a batch needs at least one instance");
+    if (ws == nullptr || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(TEUK_EINVAL, "the batch workspace must be a 256-byte aligned device pointer");
+    BatchLayout L;
+    const std::string err = batch_layout(n, descs, req, &L);
+    if (!err.empty()) return fail(TEUK_EINVAL, err);
+    if (ws_bytes < L.total)
+        return fail(TEUK_ENOMEM, "batch workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                     std::to_string(L.total));
     teuk_batch* b = new (std::nothrow) teuk_batch();
     if (b == nullptr) return fail(TEUK_ENOMEM, "host allocation failed");
     b->stream = static_cast<hipStream_t>(hip_stream);
+    char* base = static_cast<char*>(ws);
+    size_t off = L.first;
     for (int32_t k = 0; k < n; ++k) {
         teuk_ctx* c = nullptr;
-        if (int rc = teuk_init_grid(&descs[k], hip_stream, &c)) {
+        if (int rc = teuk_detail::make_ctx(&descs[k], req, hip_stream, base + off, L.inst[k], &c)) {
             const std::string msg = "instance " + std::to_string(k) + ": " + teuk_detail::g_last_error;
             free_batch(b);
             return fail(rc, msg);
         }
+        off += (L.inst[k] + 255) / 256 * 256;
         c->in_batch = true;
         b->inst.push_back(c);
     }
@@ -265,6 +325,12 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, 
         free_batch(b);
         return fail(TEUK_EINVAL, "too many tiles in one batch");
     }
+    b->d_inst = reinterpret_cast<teuk::BatchInstance*>(base + L.d_inst);
+    b->d_tiles = reinterpret_cast<int4*>(base + L.d_tiles);
+    b->d_item0 = reinterpret_cast<int*>(base + L.d_item0);
+    b->d_done = reinterpret_cast<int*>(base + L.d_done);
+    b->d_ticket = reinterpret_cast<unsigned long long*>(base + L.d_ticket);
+    b->d_abort = reinterpret_cast<int*>(base + L.d_abort);
     int dev = 0, cus = 0, khz = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -275,19 +341,15 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, void* hip_stream, 
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->h_inst_free[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(b->h_inst_free[k], b->stream);
     }
-    if (e == hipSuccess) e = hipMalloc(&b->d_inst, sizeof(teuk::BatchInstance) * n);
-    if (e == hipSuccess) e = hipMalloc(&b->d_tiles, sizeof(int4) * b->max_tiles);
-    if (e == hipSuccess) e = hipMalloc(&b->d_item0, sizeof(int) * (static_cast<size_t>(n) + 1));
-    if (e == hipSuccess) e = hipMalloc(&b->d_done, sizeof(int) * b->max_tiles);
-    if (e == hipSuccess) e = hipMalloc(&b->d_ticket, sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc(&b->d_abort, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(b->d_abort, 0, sizeof(int));
+    if (e == hipSuccess) e = teuk::launch_zero(b->d_abort, sizeof(int), b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         free_batch(b);
-        return fail(TEUK_ENOMEM, std::string("batch setup: ") + hipGetErrorString(e));
+        return hip_fail(e, "batch setup");
     }
     b->resident_waves = 8 * std::max(cus, 1);
-    b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * std::max(khz, 1));
+    b->wall_khz = std::max(khz, 1);
+    b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * b->wall_khz);
     const int seg = 16;   // each wave walks a whole strip: long segments, fewest halo rows
     if (int rc = set_batch_tiles(b, seg)) {
         const std::string msg = teuk_detail::g_last_error;
@@ -404,6 +466,21 @@ int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
     return TEUK_OK;
 }
 
+int teuk_batch_set_wait_limit(teuk_batch* b, double seconds) {
+    if (int rc = check_batch(b)) return rc;
+    if (!(seconds >= 0.0 && seconds <= 3600.0)) return fail(TEUK_EINVAL, "wait limit must be in [0, 3600] s");
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch wait limit");
+    b->wait_limit = static_cast<long long>(seconds * 1e3 * b->wall_khz);
+    drop_graphs(b);   // the limit is a kernel argument of the captured launches
+    return TEUK_OK;
+}
+
+int teuk_batch_abort(teuk_batch* b) {
+    if (int rc = check_batch(b)) return rc;
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(b->d_abort), 1, 1, b->stream), "batch abort");
+    return TEUK_OK;
+}
+
 int teuk_batch_sync(teuk_batch* b) {
     if (int rc = check_batch(b)) return rc;
     HIP_TRY(hipStreamSynchronize(b->stream), "batch sync");
@@ -411,8 +488,8 @@ int teuk_batch_sync(teuk_batch* b) {
     HIP_TRY(hipMemcpy(&flag, b->d_abort, sizeof(int), hipMemcpyDeviceToHost), "batch abort flag");
     if (flag != 0) {
         HIP_TRY(hipMemset(b->d_abort, 0, sizeof(int)), "batch abort flag clear");
-        return fail(TEUK_EDEVICE, "batched launch aborted: a dependency wait exceeded its limit; "
-                                  "instance states are invalid");
+        return fail(TEUK_EDEVICE, "batched launch aborted (a dependency wait exceeded its limit, or "
+                                  "teuk_batch_abort); instance states are invalid");
     }
     return TEUK_OK;
 }
@@ -484,29 +561,21 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
 
     // save every instance's current level, time each variant, restore
     const int seg0 = b->seg_rows, mode0 = b->mode;
-    std::vector<double2*> save;
+    // every instance's current level goes to host memory for the trials
+    std::vector<std::vector<double2>> save;
     hipError_t e = hipSuccess;
-    auto release = [&]() {
-        for (double2* p : save) (void)hipFree(p);
-        save.clear();
-    };
-    for (teuk_ctx* c : b->inst) {
-        const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
-        for (int f = 0; f < 2; ++f) {
-            double2* p = nullptr;
-            e = hipMalloc(&p, bytes);
-            if (e != hipSuccess) {
-                release();
-                return fail(TEUK_ENOMEM, std::string("batch autotune planes: ") + hipGetErrorString(e));
-            }
-            save.push_back(p);
-            e = hipMemcpyAsync(p, c->plane[c->cur][f], bytes, hipMemcpyDeviceToDevice, b->stream);
-            if (e != hipSuccess) {
-                (void)hipStreamSynchronize(b->stream);
-                release();
-                return hip_fail(e, "batch autotune save");
+    HIP_TRY(hipStreamSynchronize(b->stream), "batch autotune sync");
+    try {
+        for (teuk_ctx* c : b->inst) {
+            const size_t bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+            for (int f = 0; f < 2; ++f) {
+                save.emplace_back(bytes / sizeof(double2));
+                HIP_TRY(hipMemcpy(save.back().data(), c->plane[c->cur][f], bytes, hipMemcpyDeviceToHost),
+                        "batch autotune save");
             }
         }
+    } catch (const std::bad_alloc&) {
+        return fail(TEUK_ENOMEM, "batch autotune: host copy of the states");
     }
     // sources are detached while timing (the compact source pass is a small
     // part of an iteration, and the orbits need not extend past the call)
@@ -528,11 +597,8 @@ int teuk_batch_autotune(teuk_batch* b, const char* cache_path, teuk_tune_entry* 
             c->steps_done = steps_done0[k];
             c->has_src = src0[k] != 0;
             for (int f = 0; f < 2; ++f)
-                (void)hipMemcpyAsync(c->plane[c->cur][f], save[2 * k + f], bytes, hipMemcpyDeviceToDevice,
-                                     b->stream);
+                (void)hipMemcpy(c->plane[c->cur][f], save[2 * k + f].data(), bytes, hipMemcpyHostToDevice);
         }
-        (void)hipStreamSynchronize(b->stream);
-        release();
     };
     hipEvent_t ev[2] = {nullptr, nullptr};
     e = hipEventCreate(&ev[0]);

@@ -53,13 +53,7 @@ constexpr int kPartSteps = 64;      // adjoint iterations whose dL/dA partials a
 namespace {
 
 void free_source(teuk_ctx* c) {
-    (void)hipFree(c->d_orbit);
-    (void)hipFree(c->d_fh);
-    (void)hipFree(c->d_fn);
-    (void)hipFree(c->d_org);
-    c->d_orbit = nullptr;
-    c->d_fh = c->d_fn = nullptr;
-    c->d_org = nullptr;
+    c->d_orbit = nullptr;          // the caller's buffer
     c->h_orbit.clear();
     c->has_src = false;
     c->batch_n0 = -1;
@@ -90,52 +84,31 @@ void destroy_events(teuk_ctx* c) {
 
 constexpr size_t kTimingPool = 2048;
 
-void free_adjoint(teuk_ctx* c) {
-    for (auto& lv : c->adj)
-        for (auto& p : lv) {
-            (void)hipFree(p);
-            p = nullptr;
-        }
-    (void)hipFree(c->d_dA);
-    (void)hipFree(c->d_dA_part);
-    (void)hipFree(c->d_dA_blk);
-    c->d_dA = c->d_dA_part = c->d_dA_blk = nullptr;
-    c->adj_clock = -1;
-}
+void reset_adjoint(teuk_ctx* c) { c->adj_clock = -1; }
 
-void free_ckpt(teuk_ctx* c) {
-    for (auto p : c->snaps) (void)hipFree(p);
-    c->snaps.clear();
-    (void)hipFree(c->seg_buf);
-    (void)hipFree(c->d_ls);
-    (void)hipFree(c->d_ls_part);
+void reset_ckpt(teuk_ctx* c) {
+    c->snaps = nullptr;
     c->seg_buf = nullptr;
-    c->seg_buf_bytes = 0;
     c->d_ls = c->d_ls_part = nullptr;
     c->ckpt_valid = false;
 }
 
-void free_all(teuk_ctx* c) {
+// A context made on the library's static workspace gives it back.
+void release_static_workspace(teuk_ctx* c) { c->static_dev = -1; }
+
+void release_host_state(teuk_ctx* c) {
     destroy_events(c);
-    free_ckpt(c);
-    free_adjoint(c);
+    reset_ckpt(c);
+    reset_adjoint(c);
     free_source(c);
-    for (auto& lv : c->plane)
-        for (auto& p : lv) {
-            (void)hipFree(p);
-            p = nullptr;
-        }
-    (void)hipFree(c->d_rnode);
-    (void)hipFree(c->d_rhalf);
-    (void)hipFree(c->d_rows);
-    (void)hipFree(c->d_flag);
 }
 
 }  // namespace
 
 void teuk_detail::destroy_ctx(teuk_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
-    free_all(c);
+    release_host_state(c);
+    release_static_workspace(c);
     delete c;
 }
 
@@ -247,27 +220,76 @@ int flush_partials(teuk_ctx* c) {
     return TEUK_OK;
 }
 
+int row_pitch(int nr) { return (nr + 15) / 16 * 16; }
+
 }  // namespace
 
-extern "C" {
+std::string teuk_detail::ws_layout(const Geometry& G, int ld, const teuk_ws_request* req, WsLayout* L) {
+    *L = WsLayout{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(ld) * G.nth;
+    L->planes = take(4 * plane_bytes);
+    const size_t rbytes = sizeof(double) * teuk::RF_COUNT * static_cast<size_t>(G.nr);
+    L->rnode = take(rbytes);
+    L->rhalf = take(rbytes);
+    L->rows = take(sizeof(ThetaRow) * G.nth);
+    L->flag = take(sizeof(int));
+    if (req != nullptr && (req->sigma_r_cells != 0.0 || req->sigma_th_cells != 0.0 || req->cutoff_sigmas != 0.0)) {
+        if (!(req->sigma_r_cells > 0.0 && req->sigma_th_cells > 0.0 && req->cutoff_sigmas > 0.0))
+            return "source footprint: widths and cutoff must all be positive (or all 0 for no source)";
+        const double wr = std::ceil(2.0 * req->cutoff_sigmas * req->sigma_r_cells) + 2.0;
+        const double wt = std::ceil(2.0 * req->cutoff_sigmas * req->sigma_th_cells) + 2.0;
+        if (!(wr <= 4096.0 && wt <= 4096.0)) return "source footprint wider than 4096 cells";
+        L->win_r_cap = static_cast<int>(wr);
+        L->win_t_cap = static_cast<int>(wt);
+        const size_t tbytes = sizeof(double2) * static_cast<size_t>(L->win_r_cap) * L->win_t_cap * kSourceBatch;
+        L->fh = take(tbytes);
+        L->fn = take(tbytes);
+        L->org = take(sizeof(int4) * kSourceBatch);
+    }
+    if (req != nullptr && req->adjoint != 0) {
+        L->adjoint = true;
+        const int nstrips = (G.nr + 61) / 62;
+        const size_t max_items = static_cast<size_t>(nstrips) * ((G.nth - 3) / 4 + 1);
+        L->adj = take(4 * plane_bytes);
+        L->dA = take(sizeof(double));
+        L->dA_part = take(sizeof(double) * max_items * kPartSteps);
+        L->dA_blk = take(sizeof(double) * teuk::reduce_partials_blocks(static_cast<int>(max_items * kPartSteps)));
+    }
+    L->total = off;
+    return "";
+}
 
-const char* teuk_last_error(void) { return g_last_error.c_str(); }
-
-int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
+int teuk_detail::make_ctx(const teuk_grid_desc* d, const teuk_ws_request* req, void* hip_stream, void* ws,
+                          size_t ws_bytes, teuk_ctx** out) {
     if (d == nullptr || out == nullptr) return fail(TEUK_EINVAL, "null descriptor or output");
     *out = nullptr;
     if (!(d->ko_eps >= 0.0 && d->ko_eps <= 1.0)) return fail(TEUK_EINVAL, "need 0 <= ko_eps <= 1");
+    if (ws == nullptr) return fail(TEUK_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(TEUK_EINVAL, "workspace must be 256-byte aligned");
     teuk_ctx* c = new (std::nothrow) teuk_ctx();
     if (c == nullptr) return fail(TEUK_ENOMEM, "host allocation failed");
     std::string err = teuk::build_geometry(d->M, d->a, d->s, d->m, d->nr, d->nth, d->rs_min, d->rs_max,
                                            d->cfl, d->rs_extract, c->G);
+    if (err.empty()) err = ws_layout(c->G, row_pitch(c->G.nr), req, &c->lay);
     if (!err.empty()) {
         delete c;
         return fail(TEUK_EINVAL, err);
     }
+    if (ws_bytes < c->lay.total) {
+        const size_t need = c->lay.total;
+        delete c;
+        return fail(TEUK_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(need));
+    }
     const Geometry& G = c->G;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->ld = (G.nr + 15) / 16 * 16;
+    c->ws = static_cast<char*>(ws);
+    c->ld = row_pitch(G.nr);
     c->ko_c = d->ko_eps / 16.0;
     c->nstrips = (G.nr + 61) / 62;
     {
@@ -282,39 +304,64 @@ int teuk_init_grid(const teuk_grid_desc* d, void* hip_stream, teuk_ctx** out) {
     set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= c->nsimd) ? 8 : 4, 1);
     set_adjoint_segment(c, 4);
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    auto alloc = [&](void** p, size_t bytes) -> int {
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            free_all(c);
-            delete c;
-            return fail(TEUK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        return TEUK_OK;
-    };
-    int rc;
-    for (auto& lv : c->plane)
-        for (auto& p : lv)
-            if ((rc = alloc(reinterpret_cast<void**>(&p), plane_bytes)) != TEUK_OK) return rc;
+    const WsLayout& L = c->lay;
+    for (int l = 0; l < 2; ++l)
+        for (int f = 0; f < 2; ++f)
+            c->plane[l][f] = reinterpret_cast<double2*>(c->ws + L.planes + (2 * l + f) * plane_bytes);
+    c->d_rnode = reinterpret_cast<double*>(c->ws + L.rnode);
+    c->d_rhalf = reinterpret_cast<double*>(c->ws + L.rhalf);
+    c->d_rows = reinterpret_cast<ThetaRow*>(c->ws + L.rows);
+    c->d_flag = reinterpret_cast<int*>(c->ws + L.flag);
+    if (L.win_r_cap > 0) {
+        c->d_fh = reinterpret_cast<double2*>(c->ws + L.fh);
+        c->d_fn = reinterpret_cast<double2*>(c->ws + L.fn);
+        c->d_org = reinterpret_cast<int4*>(c->ws + L.org);
+    }
+    if (L.adjoint) {
+        for (int l = 0; l < 2; ++l)
+            for (int f = 0; f < 2; ++f)
+                c->adj[l][f] = reinterpret_cast<double2*>(c->ws + L.adj + (2 * l + f) * plane_bytes);
+        c->d_dA = reinterpret_cast<double*>(c->ws + L.dA);
+        c->d_dA_part = reinterpret_cast<double*>(c->ws + L.dA_part);
+        c->d_dA_blk = reinterpret_cast<double*>(c->ws + L.dA_blk);
+    }
     const size_t rbytes = sizeof(double) * teuk::RF_COUNT * static_cast<size_t>(G.nr);
-    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rnode), rbytes)) != TEUK_OK) return rc;
-    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rhalf), rbytes)) != TEUK_OK) return rc;
-    if ((rc = alloc(reinterpret_cast<void**>(&c->d_rows), sizeof(ThetaRow) * G.nth)) != TEUK_OK) return rc;
-    if ((rc = alloc(reinterpret_cast<void**>(&c->d_flag), sizeof(int))) != TEUK_OK) return rc;
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMemcpy(c->d_rnode, G.rnode.data(), rbytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_rhalf, G.rhalf.data(), rbytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_rows, G.rows.data(), sizeof(ThetaRow) * G.nth, hipMemcpyHostToDevice);
-    for (auto& lv : c->plane)
-        for (auto& p : lv)
-            if (e == hipSuccess) e = hipMemset(p, 0, plane_bytes);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipError_t e = hipMemcpyAsync(c->d_rnode, G.rnode.data(), rbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_rhalf, G.rhalf.data(), rbytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_rows, G.rows.data(), sizeof(ThetaRow) * G.nth, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = teuk::launch_zero(c->plane[0][0], 4 * plane_bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
-        free_all(c);
         delete c;
         return hip_fail(e, "teuk_init_grid");
     }
     *out = c;
     return TEUK_OK;
+}
+
+extern "C" {
+
+const char* teuk_last_error(void) { return g_last_error.c_str(); }
+
+int teuk_workspace_size(const teuk_grid_desc* d, const teuk_ws_request* req, size_t* bytes) {
+    if (d == nullptr || bytes == nullptr) return fail(TEUK_EINVAL, "null descriptor or output");
+    *bytes = 0;
+    if (!(d->ko_eps >= 0.0 && d->ko_eps <= 1.0)) return fail(TEUK_EINVAL, "need 0 <= ko_eps <= 1");
+    teuk::Geometry G;
+    std::string err = teuk::build_geometry(d->M, d->a, d->s, d->m, d->nr, d->nth, d->rs_min, d->rs_max, d->cfl,
+                                           d->rs_extract, G);
+    if (!err.empty()) return fail(TEUK_EINVAL, err);
+    teuk_detail::WsLayout L;
+    err = teuk_detail::ws_layout(G, row_pitch(G.nr), req, &L);
+    if (!err.empty()) return fail(TEUK_EINVAL, err);
+    *bytes = L.total;
+    return TEUK_OK;
+}
+
+int teuk_init_grid(const teuk_grid_desc* d, const teuk_ws_request* req, void* hip_stream, void* ws,
+                   size_t ws_bytes, teuk_ctx** out) {
+    return teuk_detail::make_ctx(d, req, hip_stream, ws, ws_bytes, out);
 }
 
 int teuk_destroy(teuk_ctx* c) {
@@ -412,27 +459,33 @@ int teuk_set_source(teuk_ctx* c, const teuk_source_desc* s) {
     free_source(c);
     if (s == nullptr) return TEUK_OK;
     if (s->orbit == nullptr || s->nsamples < 2) return fail(TEUK_EINVAL, "orbit needs >= 2 samples");
+    if (s->orbit_dev == nullptr) return fail(TEUK_EINVAL, "null orbit_dev (device buffer for the orbit)");
     if (!(s->sigma_r_cells > 0.0 && s->sigma_th_cells > 0.0 && s->cutoff_sigmas > 0.0))
         return fail(TEUK_EINVAL, "source widths and cutoff must be positive");
+    const double wr = std::ceil(2.0 * s->cutoff_sigmas * s->sigma_r_cells) + 2.0;
+    const double wt = std::ceil(2.0 * s->cutoff_sigmas * s->sigma_th_cells) + 2.0;
+    if (!(wr <= c->lay.win_r_cap && wt <= c->lay.win_t_cap))
+        return fail(TEUK_ENOMEM, "source footprint larger than the workspace was sized for (teuk_ws_request)");
     c->amplitude = s->amplitude;
     c->sig_r = s->sigma_r_cells * c->G.h_r;
     c->sig_th = s->sigma_th_cells * c->G.h_th;
     c->cut = s->cutoff_sigmas;
-    c->win_r = static_cast<int>(std::ceil(2.0 * s->cutoff_sigmas * s->sigma_r_cells)) + 2;
-    c->win_t = static_cast<int>(std::ceil(2.0 * s->cutoff_sigmas * s->sigma_th_cells)) + 2;
+    c->win_r = static_cast<int>(wr);
+    c->win_t = static_cast<int>(wt);
     c->nsamples = s->nsamples;
     const size_t obytes = sizeof(double) * 3 * static_cast<size_t>(s->nsamples);
-    const size_t tbytes = sizeof(double2) * static_cast<size_t>(c->win_r) * c->win_t * kSourceBatch;
-    hipError_t e = hipMalloc(&c->d_orbit, obytes);
-    if (e == hipSuccess) e = hipMalloc(&c->d_fh, tbytes);
-    if (e == hipSuccess) e = hipMalloc(&c->d_fn, tbytes);
-    if (e == hipSuccess) e = hipMalloc(&c->d_org, sizeof(int4) * kSourceBatch);
-    if (e == hipSuccess) e = hipMemcpy(c->d_orbit, s->orbit, obytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) c->h_orbit.assign(s->orbit, s->orbit + 3 * static_cast<size_t>(s->nsamples));
+    try {
+        c->h_orbit.assign(s->orbit, s->orbit + 3 * static_cast<size_t>(s->nsamples));
+    } catch (const std::bad_alloc&) {
+        return fail(TEUK_ENOMEM, "host copy of the orbit");
+    }
+    hipError_t e = hipMemcpyAsync(s->orbit_dev, s->orbit, obytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         free_source(c);
         return hip_fail(e, "set_source");
     }
+    c->d_orbit = static_cast<double*>(s->orbit_dev);
     c->has_src = true;
     return TEUK_OK;
 }
@@ -533,21 +586,8 @@ int teuk_adjoint_begin(teuk_ctx* c, const void* lam_phi, const void* lam_pi, int
     if (n_end < 0) return fail(TEUK_EINVAL, "negative n_end");
     const Geometry& G = c->G;
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    if (c->adj[0][0] == nullptr) {
-        const int max_items = c->nstrips * ((G.nth - 3) / 4 + 1);
-        hipError_t e = hipSuccess;
-        for (auto& lv : c->adj)
-            for (auto& p : lv)
-                if (e == hipSuccess) e = hipMalloc(&p, plane_bytes);
-        if (e == hipSuccess) e = hipMalloc(&c->d_dA, sizeof(double));
-        if (e == hipSuccess) e = hipMalloc(&c->d_dA_part, sizeof(double) * max_items * kPartSteps);
-        if (e == hipSuccess)
-            e = hipMalloc(&c->d_dA_blk, sizeof(double) * teuk::reduce_partials_blocks(max_items * kPartSteps));
-        if (e != hipSuccess) {
-            free_adjoint(c);
-            return fail(TEUK_ENOMEM, std::string("adjoint buffers: ") + hipGetErrorString(e));
-        }
-    }
+    if (!c->lay.adjoint)
+        return fail(TEUK_ENOMEM, "the workspace has no adjoint area (teuk_ws_request.adjoint)");
     c->adj_cur = 0;
     double2* P0 = c->adj[0][0];
     double2* P1 = c->adj[0][1];
@@ -556,19 +596,19 @@ int teuk_adjoint_begin(teuk_ctx* c, const void* lam_phi, const void* lam_pi, int
         HIP_TRY(hipMemcpy2DAsync(P0, sizeof(double2) * c->ld, lam_phi, w, w, G.nth, hipMemcpyDeviceToDevice,
                                  c->stream), "adjoint_begin copy");
     } else {
-        HIP_TRY(hipMemsetAsync(P0, 0, plane_bytes, c->stream), "adjoint_begin zero");
+        HIP_TRY(teuk::launch_zero(P0, plane_bytes, c->stream), "adjoint_begin zero");
     }
     if (lam_pi != nullptr) {
         HIP_TRY(hipMemcpy2DAsync(P1, sizeof(double2) * c->ld, lam_pi, w, w, G.nth, hipMemcpyDeviceToDevice,
                                  c->stream), "adjoint_begin copy");
     } else {
-        HIP_TRY(hipMemsetAsync(P1, 0, plane_bytes, c->stream), "adjoint_begin zero");
+        HIP_TRY(teuk::launch_zero(P1, plane_bytes, c->stream), "adjoint_begin zero");
     }
     if (gw != nullptr && n_end >= 1)
         HIP_TRY(teuk::launch_inject_column(P0, c->ld, G.nth, G.i_ext,
                                            static_cast<const double2*>(gw) + (n_end - 1) * G.nth, c->stream),
                 "adjoint_begin inject");
-    HIP_TRY(hipMemsetAsync(c->d_dA, 0, sizeof(double), c->stream), "dA zero");
+    HIP_TRY(teuk::launch_zero(c->d_dA, sizeof(double), c->stream), "dA zero");
     c->part_filled = 0;
     c->adj_clock = n_end;
     return TEUK_OK;
@@ -685,38 +725,88 @@ static int check_plan(const teuk_ctx* c, const teuk_grad_plan* p, int64_t* inter
     return TEUK_OK;
 }
 
+namespace {
+
+// Byte offsets inside a plan's checkpoint buffer: 2K snapshot planes, then
+// (state loss only) the rectangle buffer, the loss sum and its partials.
+struct CkptLayout {
+    size_t snaps = 0, seg = 0, ls = 0, ls_part = 0, total = 0;
+};
+
+CkptLayout ckpt_layout(const teuk_ctx* c, const teuk_grad_plan* p, int64_t iv) {
+    CkptLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+    const int64_t K = (p->nsteps + iv - 1) / iv;
+    L.snaps = take(2 * static_cast<size_t>(K) * plane_bytes);
+    if (p->state_weight != 0.0) {
+        const size_t wr = static_cast<size_t>(p->i1 - p->i0), hr = static_cast<size_t>(p->j1 - p->j0);
+        L.seg = take(sizeof(double2) * wr * hr * static_cast<size_t>(iv));
+        L.ls = take(sizeof(double));
+        L.ls_part = take(sizeof(double) * (c->G.nth + teuk::reduce_partials_blocks(c->G.nth)));
+    }
+    L.total = off;
+    return L;
+}
+
+// Point the context's checkpoint buffers into the plan's caller-owned buffer.
+int bind_ckpt(teuk_ctx* c, const teuk_grad_plan* p, int64_t iv) {
+    if (!c->lay.adjoint)
+        return fail(TEUK_ENOMEM, "the workspace has no adjoint area (teuk_ws_request.adjoint)");
+    const CkptLayout L = ckpt_layout(c, p, iv);
+    if (p->ckpt_dev == nullptr) return fail(TEUK_EINVAL, "null checkpoint buffer (plan.ckpt_dev)");
+    if (reinterpret_cast<uintptr_t>(p->ckpt_dev) % 256 != 0)
+        return fail(TEUK_EINVAL, "checkpoint buffer must be 256-byte aligned");
+    if (p->ckpt_bytes < L.total)
+        return fail(TEUK_ENOMEM, "checkpoint buffer of " + std::to_string(p->ckpt_bytes) + " bytes, need " +
+                                     std::to_string(L.total));
+    char* base = static_cast<char*>(p->ckpt_dev);
+    c->snaps = reinterpret_cast<double2*>(base + L.snaps);
+    const bool sl = p->state_weight != 0.0;
+    c->seg_buf = sl ? reinterpret_cast<double2*>(base + L.seg) : nullptr;
+    c->d_ls = sl ? reinterpret_cast<double*>(base + L.ls) : nullptr;
+    c->d_ls_part = sl ? reinterpret_cast<double*>(base + L.ls_part) : nullptr;
+    return TEUK_OK;
+}
+
+}  // namespace
+
+int teuk_checkpoint_size(const teuk_ctx* c, const teuk_grad_plan* plan, size_t* bytes) {
+    if (int rc = check_ctx(c)) return rc;
+    if (bytes == nullptr) return fail(TEUK_EINVAL, "null output");
+    *bytes = 0;
+    int64_t iv = 0;
+    if (int rc = check_plan(c, plan, &iv)) return rc;
+    *bytes = ckpt_layout(c, plan, iv).total;
+    return TEUK_OK;
+}
+
 int teuk_forward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, void* waveform, double* state_loss) {
     if (int rc = check_ctx(c)) return rc;
     int64_t iv = 0;
     if (int rc = check_plan(c, plan, &iv)) return rc;
     if (c->steps_done != 0) return fail(TEUK_ESTATE, "set the initial state first (no iteration taken since)");
+    c->ckpt_valid = false;
+    if (int rc = bind_ckpt(c, plan, iv)) return rc;
     const Geometry& G = c->G;
     const int64_t N = plan->nsteps;
     const int64_t K = (N + iv - 1) / iv;
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    c->ckpt_valid = false;
-    while (static_cast<int64_t>(c->snaps.size()) < 2 * K) {
-        double2* p = nullptr;
-        hipError_t e = hipMalloc(&p, plane_bytes);
-        if (e != hipSuccess) return fail(TEUK_ENOMEM, std::string("checkpoint snapshots: ") + hipGetErrorString(e));
-        c->snaps.push_back(p);
-    }
+    const size_t plane_elems = plane_bytes / sizeof(double2);
     const bool sl = plan->state_weight != 0.0;
-    if (sl && c->d_ls == nullptr) {
-        hipError_t e = hipMalloc(&c->d_ls, sizeof(double));
-        // nth row partials, then the block sums of their reduction
-        if (e == hipSuccess)
-            e = hipMalloc(&c->d_ls_part, sizeof(double) * (G.nth + teuk::reduce_partials_blocks(G.nth)));
-        if (e != hipSuccess) return fail(TEUK_ENOMEM, "state-loss buffers");
-    }
-    if (sl) HIP_TRY(hipMemsetAsync(c->d_ls, 0, sizeof(double), c->stream), "state loss zero");
+    if (sl) HIP_TRY(teuk::launch_zero(c->d_ls, sizeof(double), c->stream), "state loss zero");
     double2* wave = static_cast<double2*>(waveform);
     for (int64_t k = 0; k < K; ++k) {
         const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
-        HIP_TRY(hipMemcpyAsync(c->snaps[2 * k], c->plane[c->cur][0], plane_bytes, hipMemcpyDeviceToDevice,
-                               c->stream), "snapshot");
-        HIP_TRY(hipMemcpyAsync(c->snaps[2 * k + 1], c->plane[c->cur][1], plane_bytes, hipMemcpyDeviceToDevice,
-                               c->stream), "snapshot");
+        HIP_TRY(hipMemcpyAsync(c->snaps + (2 * k) * plane_elems, c->plane[c->cur][0], plane_bytes,
+                               hipMemcpyDeviceToDevice, c->stream), "snapshot");
+        HIP_TRY(hipMemcpyAsync(c->snaps + (2 * k + 1) * plane_elems, c->plane[c->cur][1], plane_bytes,
+                               hipMemcpyDeviceToDevice, c->stream), "snapshot");
         const bool touches = sl && !(s1 < plan->n_lo || s0 + 1 > plan->n_hi);
         if (!touches) {
             if (int rc = teuk_step_n(c, s1 - s0, wave ? wave + s0 * G.nth : nullptr)) return rc;
@@ -762,17 +852,7 @@ int teuk_backward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, const vo
     const double scale = 2.0 * plan->state_weight * dL_dLs;
     const int wr = plan->i1 - plan->i0, hr = plan->j1 - plan->j0;
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    if (sl) {
-        const size_t need = sizeof(double2) * static_cast<size_t>(wr) * hr * iv;
-        if (c->seg_buf_bytes < need) {
-            (void)hipFree(c->seg_buf);
-            c->seg_buf = nullptr;
-            c->seg_buf_bytes = 0;
-            hipError_t e = hipMalloc(&c->seg_buf, need);
-            if (e != hipSuccess) return fail(TEUK_ENOMEM, "segment buffer");
-            c->seg_buf_bytes = need;
-        }
-    }
+    const size_t plane_elems = plane_bytes / sizeof(double2);
     if (int rc = teuk_adjoint_begin(c, nullptr, nullptr, N, gw)) return rc;
     if (sl && N >= plan->n_lo && N <= plan->n_hi)
         HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld, c->plane[c->cur][0], c->ld, false, scale,
@@ -781,9 +861,9 @@ int teuk_backward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, const vo
         const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
         if (recompute) {
             // restore u^{s0} and recompute the segment, keeping Phi on the rectangle
-            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][0], c->snaps[2 * k], plane_bytes, hipMemcpyDeviceToDevice,
-                                   c->stream), "restore");
-            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][1], c->snaps[2 * k + 1], plane_bytes,
+            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][0], c->snaps + (2 * k) * plane_elems, plane_bytes,
+                                   hipMemcpyDeviceToDevice, c->stream), "restore");
+            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][1], c->snaps + (2 * k + 1) * plane_elems, plane_bytes,
                                    hipMemcpyDeviceToDevice, c->stream), "restore");
             c->steps_done = s0;
             for (int64_t m = s0; m < s1; ++m) {
@@ -909,32 +989,30 @@ int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, i
     const bool src0 = c->has_src;
     const bool timing0 = c->timing;
     const int seg0 = c->seg_rows, k0 = c->k_steps;
-    double2* save[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (int rc = flush_timing(c)) return rc;
-    hipError_t e = hipMalloc(&save[0], plane_bytes);
-    if (e == hipSuccess) e = hipMalloc(&save[1], plane_bytes);
-    if (e != hipSuccess) {
-        (void)hipFree(save[0]);
-        return fail(TEUK_ENOMEM, std::string("autotune planes: ") + hipGetErrorString(e));
+    // the current level goes to host memory for the trials
+    std::vector<double2> save[2];
+    try {
+        for (auto& v : save) v.resize(plane_bytes / sizeof(double2));
+    } catch (const std::bad_alloc&) {
+        return fail(TEUK_ENOMEM, "autotune: host copy of the state");
     }
+    HIP_TRY(hipStreamSynchronize(c->stream), "autotune sync");
+    for (int f = 0; f < 2; ++f)
+        HIP_TRY(hipMemcpy(save[f].data(), c->plane[cur0][f], plane_bytes, hipMemcpyDeviceToHost), "autotune save");
     auto restore = [&]() {
         (void)hipStreamSynchronize(c->stream);
         c->cur = cur0;
-        (void)hipMemcpyAsync(c->plane[cur0][0], save[0], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
-        (void)hipMemcpyAsync(c->plane[cur0][1], save[1], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
-        (void)hipStreamSynchronize(c->stream);
+        for (int f = 0; f < 2; ++f)
+            (void)hipMemcpy(c->plane[cur0][f], save[f].data(), plane_bytes, hipMemcpyHostToDevice);
         c->steps_done = steps0;
         c->has_src = src0;
         c->timing = timing0;
-        (void)hipFree(save[0]);
-        (void)hipFree(save[1]);
         for (auto& x : ev)
             if (x != nullptr) (void)hipEventDestroy(x);
     };
-    e = hipMemcpyAsync(save[0], c->plane[cur0][0], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(save[1], c->plane[cur0][1], plane_bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    hipError_t e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e != hipSuccess) {
         restore();
@@ -1001,7 +1079,7 @@ int teuk_kernel_timing(teuk_ctx* c, double* total_ms, int64_t* launches) {
 
 int teuk_check_finite(teuk_ctx* c) {
     if (int rc = check_ctx(c)) return rc;
-    HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "finite flag");
+    HIP_TRY(teuk::launch_zero(c->d_flag, sizeof(int), c->stream), "finite flag");
     HIP_TRY(teuk::launch_finite(c->plane[c->cur][0], c->plane[c->cur][1], c->G.nr, c->G.nth, c->ld,
                                 c->d_flag, c->stream), "finite kernel");
     int flag = 0;

@@ -20,7 +20,8 @@ extern thread_local std::string g_last_error;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 
-// Release every device resource of a context and delete it (no ownership check).
+// Release a context's events and host state and delete it (no ownership
+// check); its device memory is the caller's workspace and stays with the caller.
 void destroy_ctx(teuk_ctx* c);
 
 // Make the source windows of iteration n resident and return their slot in
@@ -29,18 +30,41 @@ void destroy_ctx(teuk_ctx* c);
 // resident batch already holds n at amplitude amp.
 int ensure_source(teuk_ctx* c, int64_t n, double amp, bool backward, int64_t span, size_t* slot);
 
-}  // namespace teuk_detail
-
 #define HIP_TRY(expr, what)                                                  \
     do {                                                                     \
         hipError_t _e = (expr);                                              \
         if (_e != hipSuccess) return teuk_detail::hip_fail(_e, what);        \
     } while (0)
 
+// Byte offsets of a context's device buffers inside its caller-owned
+// workspace (every offset a multiple of 256).
+struct WsLayout {
+    size_t planes = 0;        // 4 state planes: [level][Phi, Pi]
+    size_t rnode = 0, rhalf = 0, rows = 0, flag = 0;
+    size_t fh = 0, fn = 0, org = 0;        // source windows (win_r_cap x win_t_cap per iteration)
+    size_t adj = 0;                        // 4 adjoint planes
+    size_t dA = 0, dA_part = 0, dA_blk = 0;
+    size_t total = 0;
+    int win_r_cap = 0, win_t_cap = 0;      // 0: no room for a source
+    bool adjoint = false;
+};
+
+// Layout of the workspace for a grid and request; "" or an error message.
+std::string ws_layout(const teuk::Geometry& G, int ld, const teuk_ws_request* req, WsLayout* L);
+
+// Context set up on a workspace (no device allocation); on failure nothing is left behind.
+int make_ctx(const teuk_grid_desc* d, const teuk_ws_request* req, void* hip_stream, void* ws, size_t ws_bytes,
+             teuk_ctx** out);
+
+}  // namespace teuk_detail
+
 struct teuk_ctx {
     teuk::Geometry G;
     bool in_batch = false;          // owned by a teuk_batch: teuk_destroy refuses it
+    int static_dev = -1;            // device whose static workspace this context holds (-1: caller's workspace)
     hipStream_t stream = nullptr;
+    char* ws = nullptr;             // caller-owned workspace (never freed here)
+    teuk_detail::WsLayout lay;
     int ld = 0;
     double2* plane[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [level][Phi, Pi]
     int cur = 0;
@@ -77,12 +101,11 @@ struct teuk_ctx {
     double* d_dA_blk = nullptr;    // block sums of the partials (fixed-order reduction)
     int part_items = 0;            // partials per iteration (waves of the adjoint launch)
     int part_filled = 0;           // iterations written since the last reduction
-    // checkpointed gradient
-    std::vector<double2*> snaps;   // 2 planes per snapshot: [2k] Phi, [2k+1] Pi
+    // checkpointed gradient (buffers carved from the plan's caller-owned checkpoint buffer)
+    double2* snaps = nullptr;      // 2 planes per snapshot: [2k] Phi, [2k+1] Pi, plane_bytes apart
     double2* seg_buf = nullptr;    // Phi on the loss rectangle, one slot per segment iteration
-    size_t seg_buf_bytes = 0;
     double* d_ls = nullptr;        // accumulated sum |Phi|^2 over the rectangle
-    double* d_ls_part = nullptr;   // per-row partials (nth)
+    double* d_ls_part = nullptr;   // per-row partials (nth), then their block sums
     bool ckpt_valid = false;
     teuk_grad_plan ckpt_plan{};
     // kernel timing (measurement aid)

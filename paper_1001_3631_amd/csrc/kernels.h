@@ -162,5 +162,7 @@ hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t str
 hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream);
 hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,
                          hipStream_t stream);
+// Zero bytes (a multiple of 4) at p (16-byte aligned) on the stream.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 
 }  // namespace teuk

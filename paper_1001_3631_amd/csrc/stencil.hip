@@ -10,6 +10,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "kernels.h"
@@ -345,9 +347,31 @@ __global__ void __launch_bounds__(256) finite_kernel(const double2* __restrict__
     if (!isfinite(u.x) || !isfinite(u.y) || !isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
 }
 
+// Clears n16 16-byte words and then tail 4-byte words after them (a kernel,
+// not hipMemsetAsync, so that the clear is an ordinary kernel node when a
+// caller captures the stream).
+__global__ void zero_kernel(uint4* p, size_t n16, unsigned int* tail, int ntail) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n16; k += stride)
+        p[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < ntail) tail[threadIdx.x] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    const int ntail = static_cast<int>((bytes - 16 * n16) / 4);
+    const size_t blocks = std::min<size_t>((n16 + 255) / 256 + 1, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<uint4*>(p), n16, reinterpret_cast<unsigned int*>(static_cast<char*>(p) + 16 * n16),
+                       ntail);
+    return hipGetLastError();
+}
 
 bool valid_segment_rows(int seg) {
     for (int v : kSegVariants)

@@ -26,29 +26,67 @@ def _need_device(t, shape, name):
         raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
 
 
+def ws_request(source_footprint=(2.0, 2.0, 8.0), adjoint=True):
+    """teuk_ws_request: the largest source footprint (sigma_r_cells,
+    sigma_th_cells, cutoff_sigmas; None = no source) and whether the adjoint
+    area is needed."""
+    sr, st, cut = source_footprint if source_footprint is not None else (0.0, 0.0, 0.0)
+    return L.WsRequest(float(sr), float(st), float(cut), 1 if adjoint else 0)
+
+
+def device_buffer(nbytes):
+    """Caller-owned device memory for the library: a torch uint8 tensor
+    (torch's allocator hands out blocks aligned to at least 256 bytes)."""
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+    if t.data_ptr() % 256 != 0:
+        raise RuntimeError("device buffer not 256-byte aligned")
+    return t
+
+
+def grid_desc(g):
+    return L.GridDesc(float(g["M"]), float(g["a"]), int(g["s"]), int(g["m"]), int(g["nr"]), int(g["nth"]),
+                      float(g["rs_min"]), float(g["rs_max"]), float(g.get("cfl", 0.5)),
+                      float(g["rs_max"] if g.get("rs_extract") is None else g["rs_extract"]),
+                      float(g.get("ko_eps", 0.5)))
+
+
 class Engine:
     """One evolving instance.
 
     Parameters follow teuk_grid_desc: M, a, s, m, nr, nth, rs_min, rs_max,
-    cfl, rs_extract, ko_eps.
+    cfl, rs_extract, ko_eps.  The context lives in a device workspace that
+    this object owns (a torch tensor), sized by teuk_workspace_size for the
+    largest source footprint it will take and, with adjoint=True, the
+    reverse sweep.
     """
 
     def __init__(self, M, a, s, m, nr, nth, rs_min, rs_max, cfl=0.5, rs_extract=None,
-                 ko_eps=0.5, stream=None):
+                 ko_eps=0.5, stream=None, source_footprint=(2.0, 2.0, 8.0), adjoint=True):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the engine needs a HIP device")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        desc = L.GridDesc(float(M), float(a), int(s), int(m), int(nr), int(nth), float(rs_min),
-                          float(rs_max), float(cfl),
-                          float(rs_max if rs_extract is None else rs_extract), float(ko_eps))
+        desc = grid_desc(dict(M=M, a=a, s=s, m=m, nr=nr, nth=nth, rs_min=rs_min, rs_max=rs_max, cfl=cfl,
+                              rs_extract=rs_extract, ko_eps=ko_eps))
+        req = ws_request(source_footprint, adjoint)
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.teuk_workspace_size(ctypes.byref(desc), ctypes.byref(req), ctypes.byref(nbytes)))
+        self._ws = device_buffer(nbytes.value)
         ctx = ctypes.c_void_p()
-        L.check(self._lib.teuk_init_grid(ctypes.byref(desc), ctypes.c_void_p(self.stream.cuda_stream),
-                                         ctypes.byref(ctx)))
+        L.check(self._lib.teuk_init_grid(ctypes.byref(desc), ctypes.byref(req),
+                                         ctypes.c_void_p(self.stream.cuda_stream), _ptr(self._ws),
+                                         nbytes.value, ctypes.byref(ctx)))
         self.ctx = ctx
         self.m = int(m)
         self._orbit = None
+        self._orbit_dev = None
+        self._ckpt_buf = None
         self._gw = None
+        self.checkpoint_generation = 0   # counts forward_checkpointed calls
+
+    @property
+    def workspace_bytes(self):
+        return self._ws.numel()
 
     @classmethod
     def _borrowed(cls, lib, ctx, m, stream):
@@ -59,7 +97,10 @@ class Engine:
         e.ctx = ctx
         e.m = int(m)
         e._orbit = None
+        e._orbit_dev = None
+        e._ckpt_buf = None
         e._gw = None
+        e.checkpoint_generation = 0
         e._borrowed_ctx = True
         return e
 
@@ -75,6 +116,10 @@ class Engine:
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self._lib.teuk_destroy(self.ctx)
             self.ctx = None
+        # the buffers go only after the context is gone
+        self._orbit_dev = None
+        self._ckpt_buf = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -139,13 +184,16 @@ class Engine:
         if orbit is None:
             L.check(self._lib.teuk_set_source(self.ctx, None))
             self._orbit = None
+            self._orbit_dev = None
             return
         orbit = np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3)
-        self._orbit = orbit
+        dev = torch.empty(orbit.size, dtype=torch.float64, device="cuda")
         desc = L.SourceDesc(float(amplitude), float(sigma_r_cells), float(sigma_th_cells),
                             float(cutoff_sigmas), orbit.shape[0],
-                            orbit.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                            orbit.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(dev))
         L.check(self._lib.teuk_set_source(self.ctx, ctypes.byref(desc)))
+        self._orbit = orbit
+        self._orbit_dev = dev
 
     def set_amplitude(self, amplitude):
         L.check(self._lib.teuk_set_amplitude(self.ctx, float(amplitude)))
@@ -228,10 +276,28 @@ class Engine:
     # -- checkpointed gradient ----------------------------------------------
     def _plan(self, nsteps, interval, state_loss, force_recompute):
         sl = state_loss or {}
-        return L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
+        plan = L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
                           int(sl.get("i0", 0)), int(sl.get("i1", 0)), int(sl.get("j0", 0)),
                           int(sl.get("j1", 0)), int(sl.get("n_lo", 0)), int(sl.get("n_hi", 0)),
-                          1 if force_recompute else 0)
+                          1 if force_recompute else 0, None, 0)
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.teuk_checkpoint_size(self.ctx, ctypes.byref(plan), ctypes.byref(nbytes)))
+        if self._ckpt_buf is None or self._ckpt_buf.numel() < nbytes.value:
+            self._ckpt_buf = None
+            self._ckpt_buf = device_buffer(nbytes.value)
+        plan.ckpt_dev = self._ckpt_buf.data_ptr()
+        plan.ckpt_bytes = self._ckpt_buf.numel()
+        return plan
+
+    def checkpoint_bytes(self, nsteps, interval=0, state_loss=None):
+        """Bytes of checkpoint buffer a checkpointed run of nsteps needs."""
+        sl = state_loss or {}
+        plan = L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
+                          int(sl.get("i0", 0)), int(sl.get("i1", 0)), int(sl.get("j0", 0)),
+                          int(sl.get("j1", 0)), int(sl.get("n_lo", 0)), int(sl.get("n_hi", 0)), 0, None, 0)
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.teuk_checkpoint_size(self.ctx, ctypes.byref(plan), ctypes.byref(nbytes)))
+        return nbytes.value
 
     def forward_checkpointed(self, nsteps, interval=0, state_loss=None, force_recompute=False):
         """Run nsteps iterations keeping snapshots for the reverse sweep.
@@ -239,6 +305,7 @@ class Engine:
         L_s = weight * sum_{n=n_lo..n_hi} sum_rect |Phi^n|^2, or None.
         Returns (waveform, L_s)."""
         self._ckpt = self._plan(nsteps, interval, state_loss, force_recompute)
+        self.checkpoint_generation += 1
         nth = self.shape[0]
         w = torch.empty((int(nsteps), nth), dtype=torch.complex128, device="cuda")
         ls = ctypes.c_double(0.0)
@@ -283,7 +350,7 @@ class Batch:
     PERSISTENT = L.BATCH_PERSISTENT
     PER_ITERATION = L.BATCH_PER_ITERATION
 
-    def __init__(self, grids, stream=None):
+    def __init__(self, grids, stream=None, source_footprint=(2.0, 2.0, 8.0), adjoint=False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the engine needs a HIP device")
@@ -291,11 +358,14 @@ class Batch:
         n = len(grids)
         descs = (L.GridDesc * n)()
         for k, g in enumerate(grids):
-            descs[k] = L.GridDesc(float(g["M"]), float(g["a"]), int(g["s"]), int(g["m"]), int(g["nr"]),
-                                  int(g["nth"]), float(g["rs_min"]), float(g["rs_max"]), float(g.get("cfl", 0.5)),
-                                  float(g.get("rs_extract", g["rs_max"])), float(g.get("ko_eps", 0.5)))
+            descs[k] = grid_desc(g)
+        req = ws_request(source_footprint, adjoint)
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.teuk_batch_workspace_size(n, descs, ctypes.byref(req), ctypes.byref(nbytes)))
+        self._ws = device_buffer(nbytes.value)
         ctx = ctypes.c_void_p()
-        L.check(self._lib.teuk_batch_create(n, descs, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        L.check(self._lib.teuk_batch_create(n, descs, ctypes.byref(req), ctypes.c_void_p(self.stream.cuda_stream),
+                                            _ptr(self._ws), nbytes.value, ctypes.byref(ctx)))
         self.ctx = ctx
         self.instances = []
         for k, g in enumerate(grids):
@@ -309,6 +379,7 @@ class Batch:
                 e.close()
             self._lib.teuk_batch_destroy(self.ctx)
             self.ctx = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -354,6 +425,16 @@ class Batch:
 
     def sync(self):
         L.check(self._lib.teuk_batch_sync(self.ctx))
+
+    def set_wait_limit(self, seconds):
+        """Device wall-clock time a dependency wait of the persistent mode
+        may take before the launch gives up (default 2 s)."""
+        L.check(self._lib.teuk_batch_set_wait_limit(self.ctx, float(seconds)))
+
+    def abort(self):
+        """Make the persistent launches queued from here on exit at once;
+        the next sync() raises TEUK_EDEVICE."""
+        L.check(self._lib.teuk_batch_abort(self.ctx))
 
     def autotune(self, cache_path=None):
         """Measure every (mode, seg_rows) (or take it from the cache file) and

@@ -45,15 +45,90 @@ def _desc(**kw):
 def test_invalid_descriptor_is_rejected_before_any_device_call(bad):
     lib = L.load()
     ctx = ctypes.c_void_p()
-    rc = lib.teuk_init_grid(ctypes.byref(_desc(**bad)), None, ctypes.byref(ctx))
+    nbytes = ctypes.c_size_t(123)
+    assert lib.teuk_workspace_size(ctypes.byref(_desc(**bad)), None, ctypes.byref(nbytes)) == L.TEUK_EINVAL
+    assert nbytes.value == 0
+    # a workspace pointer that is never dereferenced: validation comes first
+    rc = lib.teuk_init_grid(ctypes.byref(_desc(**bad)), None, None, ctypes.c_void_p(FAKE_WS), 1 << 40,
+                            ctypes.byref(ctx))
     assert rc == L.TEUK_EINVAL
     assert ctx.value is None
     assert len(lib.teuk_last_error()) > 0
 
 
+# An aligned address that the library must never touch in these tests: every
+# call below fails its checks before any device work.
+FAKE_WS = 1 << 36
+
+
+def _ws_size(desc, req=None):
+    lib = L.load()
+    nbytes = ctypes.c_size_t()
+    assert lib.teuk_workspace_size(ctypes.byref(desc), ctypes.byref(req) if req is not None else None,
+                                   ctypes.byref(nbytes)) == L.TEUK_OK
+    return nbytes.value
+
+
+def test_workspace_size_covers_what_is_requested():
+    d = _desc()
+    nr, nth = d.nr, d.nth
+    ld = (nr + 15) // 16 * 16
+    plane = 16 * ld * nth
+    base = _ws_size(d)
+    assert base >= 4 * plane
+    src = _ws_size(d, L.WsRequest(2.0, 2.0, 8.0, 0))
+    win = (2 * 8 * 2 + 2) ** 2 * 16 * 256          # two window tables of 34 x 34, 256 iterations
+    assert src - base >= 2 * win
+    adj = _ws_size(d, L.WsRequest(0.0, 0.0, 0.0, 1))
+    assert adj - base >= 4 * plane
+    both = _ws_size(d, L.WsRequest(2.0, 2.0, 8.0, 1))
+    assert both == src + adj - base
+    assert all(v % 256 == 0 for v in (base, src, adj, both))
+    # a half-specified footprint is refused
+    lib = L.load()
+    nbytes = ctypes.c_size_t()
+    assert lib.teuk_workspace_size(ctypes.byref(d), ctypes.byref(L.WsRequest(2.0, 0.0, 8.0, 0)),
+                                   ctypes.byref(nbytes)) == L.TEUK_EINVAL
+
+
+def test_small_or_misaligned_workspace_is_refused_before_any_device_call():
+    lib = L.load()
+    d = _desc()
+    req = L.WsRequest(2.0, 2.0, 8.0, 1)
+    need = _ws_size(d, req)
+    ctx = ctypes.c_void_p()
+    rc = lib.teuk_init_grid(ctypes.byref(d), ctypes.byref(req), None, ctypes.c_void_p(FAKE_WS), need - 1,
+                            ctypes.byref(ctx))
+    assert rc == L.TEUK_ENOMEM and ctx.value is None
+    assert str(need) in lib.teuk_last_error().decode()
+    rc = lib.teuk_init_grid(ctypes.byref(d), ctypes.byref(req), None, ctypes.c_void_p(FAKE_WS + 64), need,
+                            ctypes.byref(ctx))
+    assert rc == L.TEUK_EINVAL and ctx.value is None
+    rc = lib.teuk_init_grid(ctypes.byref(d), ctypes.byref(req), None, None, need, ctypes.byref(ctx))
+    assert rc == L.TEUK_EINVAL and ctx.value is None
+
+
+def test_batch_workspace_is_the_sum_of_its_parts_and_checked():
+    lib = L.load()
+    grids = [_desc(), _desc(nr=333, nth=41, m=3), _desc(nr=5, nth=7)]
+    descs = (L.GridDesc * 3)(*grids)
+    req = L.WsRequest(2.0, 2.0, 8.0, 0)
+    nbytes = ctypes.c_size_t()
+    assert lib.teuk_batch_workspace_size(3, descs, ctypes.byref(req), ctypes.byref(nbytes)) == L.TEUK_OK
+    parts = sum(_ws_size(g, req) for g in grids)
+    assert parts < nbytes.value < parts + 64 * 1024
+    b = ctypes.c_void_p()
+    rc = lib.teuk_batch_create(3, descs, ctypes.byref(req), None, ctypes.c_void_p(FAKE_WS), nbytes.value - 256,
+                               ctypes.byref(b))
+    assert rc == L.TEUK_ENOMEM and b.value is None
+    bad = (L.GridDesc * 2)(_desc(), _desc(a=1.5))
+    assert lib.teuk_batch_workspace_size(2, bad, None, ctypes.byref(nbytes)) == L.TEUK_EINVAL
+    assert b"instance 1" in lib.teuk_last_error()
+
+
 def test_null_arguments_are_rejected():
     lib = L.load()
-    assert lib.teuk_init_grid(None, None, None) == L.TEUK_EINVAL
+    assert lib.teuk_init_grid(None, None, None, None, 0, None) == L.TEUK_EINVAL
     assert lib.teuk_step_n(None, 1, None) == L.TEUK_EINVAL
     assert lib.teuk_get_info(None, None) == L.TEUK_EINVAL
     assert lib.teuk_destroy(None) == L.TEUK_OK

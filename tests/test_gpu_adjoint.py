@@ -159,6 +159,63 @@ def test_autograd_function_gradients():
     assert abs(float(A.grad) - gA) <= 1e-13 * abs(gA)
 
 
+def test_autograd_function_matches_oracle_reverse_sweep():
+    """torch.autograd through TeukEvolve against the oracle's own reverse
+    sweep (not the engine's adjoint): the loss sum |w - y|^2 differentiated
+    with respect to the initial data and the source amplitude."""
+    from paper_1001_3631_amd.autograd import evolve
+    grid, n = _adjoint_case(80)
+    g = T.Grid(**grid)
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    y = W.target_noise((n, g.nth), 0.05, seed=4)
+    src = oracle_source(g, SRC, n)
+    w = T.evolve(g, phi0, pi0, n, src)[2]
+    _, gw = T.waveform_loss(w, y)
+    rgp, rgq, rdA = T.adjoint_evolve(g, gw, n, src)
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    P0 = to_dev(phi0).requires_grad_(True)
+    Q0 = to_dev(pi0).requires_grad_(True)
+    A = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = torch.sum(torch.abs(evolve(P0, Q0, A, eng, n) - to_dev(y)) ** 2)
+    L.backward()
+    e = (rel(host(P0.grad), rgp), rel(host(Q0.grad), rgq), abs(float(A.grad) - rdA) / abs(rdA))
+    print("autograd vs oracle reverse sweep (grad Phi0, grad Pi0, dL/dA):", e)
+    assert max(e) <= 1e-12, e
+
+
+def test_checkpointed_autograd_refuses_snapshots_of_a_later_forward():
+    """Two checkpointed forwards on one engine: the engine holds the second
+    one's snapshots, so the first node's backward must refuse to run, and
+    the second node's backward still gives the right gradient."""
+    from paper_1001_3631_amd.autograd import TeukEvolveCheckpointed
+    grid, n = _adjoint_case(40)
+    g = T.Grid(**grid)
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    sl = dict(STATE_LOSS, n_lo=10, n_hi=30)
+    A = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    P0 = to_dev(phi0).requires_grad_(True)
+    Q0 = to_dev(pi0).requires_grad_(True)
+    _, ls1 = TeukEvolveCheckpointed.apply(P0, Q0, A, eng, n, sl, 0)
+    P1 = to_dev(0.5 * phi0).requires_grad_(True)
+    Q1 = to_dev(0.5 * pi0).requires_grad_(True)
+    _, ls2 = TeukEvolveCheckpointed.apply(P1, Q1, A, eng, n, sl, 0)
+    with pytest.raises(RuntimeError, match="another checkpointed forward"):
+        ls1.backward()
+    ls2.backward()
+    # reference: the same loss and engine, one forward and one backward
+    eng2 = gpu_engine(grid)
+    gpu_source(eng2, grid, SRC, n)
+    P2 = to_dev(0.5 * phi0).requires_grad_(True)
+    Q2 = to_dev(0.5 * pi0).requires_grad_(True)
+    A2 = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    _, ls3 = TeukEvolveCheckpointed.apply(P2, Q2, A2, eng2, n, sl, 0)
+    ls3.backward()
+    assert torch.equal(P1.grad, P2.grad) and torch.equal(Q1.grad, Q2.grad)
+
+
 # ---------------------------------------------------------------------------
 # Checkpointed gradient (snapshots + recompute) for losses on the states
 # ---------------------------------------------------------------------------

@@ -300,3 +300,65 @@ def test_batch_autotune_restores_states(tmp_path):
     assert len(hit) == 1 and hit[0][:2] == table[0][:2]
     assert (b.seg_rows, b.mode) == table[0][:2]
     b.close()
+
+
+def test_persistent_abort_is_reported_and_cleared():
+    """The abort path of the persistent kernel, forced from the host: with the
+    abort flag stored before the launch every wave leaves at its first pass,
+    teuk_batch_sync reports TEUK_EDEVICE once and clears the flag, and the
+    next launch on the same batch runs normally (bitwise equal to single
+    instances)."""
+    from paper_1001_3631_amd._lib import TEUK_EDEVICE, TeukError
+    grids = MIXED[:3]
+    states = [W.random_state(g["nth"], g["nr"], seed=71 + k) for k, g in enumerate(grids)]
+    ref = single_runs(grids, states, [6])
+    b = make_batch(grids)
+    b.set_mode(0)
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    b.abort()
+    b.step(6, waveform=False)
+    with pytest.raises(TeukError) as ei:
+        b.sync()
+    assert ei.value.code == TEUK_EDEVICE
+    b.sync()                                    # reported once, then cleared
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    w = b.step(6)
+    b.sync()
+    for k, e in enumerate(b.instances):
+        p, q = e.get_state()
+        assert_bitwise((host(w[k]), host(p), host(q)), ref[k])
+    b.close()
+
+
+def test_persistent_wait_limit_zero_ends_the_launch():
+    """A zero wait limit makes every dependency wait that is not satisfied at
+    its first check give up: the launch still ends (every wave leaves), and
+    sync reports either a clean run or the abort.  With the default limit
+    restored the batch runs normally again."""
+    from paper_1001_3631_amd._lib import TEUK_EDEVICE, TeukError
+    grids = [W.KERR_EMRI["grid"], MIXED[0]]
+    states = [W.random_state(g["nth"], g["nr"], seed=81 + k) for k, g in enumerate(grids)]
+    ref = single_runs(grids, states, [4])
+    b = make_batch(grids)
+    b.set_mode(0)
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    b.set_wait_limit(0.0)
+    b.step(4, waveform=False)
+    try:
+        b.sync()
+        print("zero wait limit: no wait gave up")
+    except TeukError as ex:
+        assert ex.code == TEUK_EDEVICE
+        print("zero wait limit: abort reported")
+    b.set_wait_limit(2.0)
+    for e, (phi, pi) in zip(b.instances, states):
+        e.set_state(to_dev(phi), to_dev(pi))
+    w = b.step(4)
+    b.sync()
+    for k, e in enumerate(b.instances):
+        p, q = e.get_state()
+        assert_bitwise((host(w[k]), host(p), host(q)), ref[k])
+    b.close()
