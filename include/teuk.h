@@ -139,6 +139,22 @@ int teuk_workspace_size(const teuk_grid_desc* desc, const teuk_ws_request* req, 
 int teuk_init_grid(const teuk_grid_desc* desc, const teuk_ws_request* req, void* hip_stream,
                    void* dev_workspace, size_t ws_bytes, teuk_ctx** out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): teuk_init_grid with
+ * the workspace taken from the library's own static device array of 64 MiB
+ * (one per GPU, held until the process ends) instead of a caller's buffer.
+ * Allocates no device memory: hipGetSymbolAddress finds the array once per
+ * device; the context object itself and its host-side tables are ordinary
+ * host memory.  At most one such context per device at a time (TEUK_ESTATE
+ * while another holds it; teuk_destroy gives it back), so contexts cannot
+ * overlap on one GPU; the array keeps the previous context's contents, and
+ * the state planes are cleared at set-up.  TEUK_ENOMEM if
+ * teuk_workspace_size(desc, req) exceeds 64 MiB (e.g. 6400 x 128 with a
+ * source fits, with the adjoint area it does not).  Other arguments and
+ * errors as teuk_init_grid. */
+int teuk_init_grid_static(const teuk_grid_desc* desc, const teuk_ws_request* req, void* hip_stream,
+                          teuk_ctx** out);
+
 /* Release the context (host state and events); the workspace and every other
  * caller buffer stay with the caller.  Synchronizes the stream.  NULL is a
  * no-op. */

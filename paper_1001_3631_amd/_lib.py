@@ -87,6 +87,8 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_size_t)]),
     "teuk_init_grid": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(WsRequest), _P, _P,
                                       ctypes.c_size_t, ctypes.POINTER(_CTX)]),
+    "teuk_init_grid_static": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(WsRequest), _P,
+                                             ctypes.POINTER(_CTX)]),
     "teuk_destroy": (ctypes.c_int, [_CTX]),
     "teuk_get_info": (ctypes.c_int, [_CTX, ctypes.POINTER(Info)]),
     "teuk_set_state": (ctypes.c_int, [_CTX, _P, _P]),

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -93,8 +94,17 @@ void reset_ckpt(teuk_ctx* c) {
     c->ckpt_valid = false;
 }
 
+// Devices whose static workspace a live context holds (teuk_init_grid_static).
+std::mutex g_static_mutex;
+std::vector<int> g_static_busy;
+
 // A context made on the library's static workspace gives it back.
-void release_static_workspace(teuk_ctx* c) { c->static_dev = -1; }
+void release_static_workspace(teuk_ctx* c) {
+    if (c->static_dev < 0) return;
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    g_static_busy.erase(std::remove(g_static_busy.begin(), g_static_busy.end(), c->static_dev), g_static_busy.end());
+    c->static_dev = -1;
+}
 
 void release_host_state(teuk_ctx* c) {
     destroy_events(c);
@@ -362,6 +372,35 @@ int teuk_workspace_size(const teuk_grid_desc* d, const teuk_ws_request* req, siz
 int teuk_init_grid(const teuk_grid_desc* d, const teuk_ws_request* req, void* hip_stream, void* ws,
                    size_t ws_bytes, teuk_ctx** out) {
     return teuk_detail::make_ctx(d, req, hip_stream, ws, ws_bytes, out);
+}
+
+int teuk_init_grid_static(const teuk_grid_desc* d, const teuk_ws_request* req, void* hip_stream, teuk_ctx** out) {
+    if (d == nullptr || out == nullptr) return fail(TEUK_EINVAL, "null descriptor or output");
+    *out = nullptr;
+    size_t need = 0;
+    if (int rc = teuk_workspace_size(d, req, &need)) return rc;
+    if (need > teuk::kStaticWorkspaceBytes)
+        return fail(TEUK_ENOMEM, "grid needs a workspace of " + std::to_string(need) +
+                                     " bytes; the static workspace holds " +
+                                     std::to_string(teuk::kStaticWorkspaceBytes));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "static workspace device");
+    void* ws = nullptr;
+    HIP_TRY(teuk::static_workspace(&ws), "static workspace address");
+    {
+        std::lock_guard<std::mutex> lock(g_static_mutex);
+        if (std::find(g_static_busy.begin(), g_static_busy.end(), dev) != g_static_busy.end())
+            return fail(TEUK_ESTATE, "the static workspace of this device is held by another context");
+        g_static_busy.push_back(dev);
+    }
+    const int rc = teuk_detail::make_ctx(d, req, hip_stream, ws, teuk::kStaticWorkspaceBytes, out);
+    if (rc != TEUK_OK) {
+        std::lock_guard<std::mutex> lock(g_static_mutex);
+        g_static_busy.erase(std::remove(g_static_busy.begin(), g_static_busy.end(), dev), g_static_busy.end());
+        return rc;
+    }
+    (*out)->static_dev = dev;
+    return TEUK_OK;
 }
 
 int teuk_destroy(teuk_ctx* c) {

@@ -165,4 +165,9 @@ hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, in
 // Zero bytes (a multiple of 4) at p (16-byte aligned) on the stream.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 
+// The library's static device workspace (static_ws.hip): its size, and its
+// device address on the current device (looked up once per device).
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+hipError_t static_workspace(void** ptr);
+
 }  // namespace teuk
