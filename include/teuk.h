@@ -448,6 +448,44 @@ int teuk_batch_autotune(teuk_batch* batch, const char* cache_path, teuk_tune_ent
 int teuk_set_kernel_timing(teuk_ctx* ctx, int enable);
 int teuk_kernel_timing(teuk_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* ---- Radiated energy and momentum -----------------------------------------
+ * The waves carry energy, linear and angular momentum away from the binary,
+ * which recoils (Sec. 3.2, closing paragraph, and its figure of the kick).
+ * From the extracted waveforms of several m modes of one system (Phi at the
+ * extraction column, which stands for r psi_4 at large r: for s = -2,
+ * Psi = rho^-4 psi_4 and Psi = e^{i m phi~} r^3 Phi), with the news integral
+ * H_m = int_0^t Phi_m dt' and K_m = int_0^t H_m dt' (trapezoidal rule):
+ *   dE/dt           = 1/2 sum_m int |H_m|^2 sin dtheta
+ *   d(Px + i Py)/dt = 1/2 sum_m int H_m conj(H_{m+1}) sin^2 dtheta
+ *   dPz/dt          = 1/2 sum_m int |H_m|^2 cos sin dtheta
+ *   dJz/dt          = 1/2 sum_m m Im int conj(H_m) K_m sin dtheta
+ * (the standard psi_4 flux integrals over the sphere, their phi integrals
+ * done exactly on the Fourier modes; theta integrals by the trapezoidal
+ * rule on the rows theta_j = j pi/(nth - 1)).
+ *   nmodes  1..16 waveforms; m (host array) their azimuthal numbers, distinct;
+ *   waves   host array of nmodes device pointers, each (nsteps + 1) x nth
+ *           complex128: row n = Phi at the extraction column at t = n dt
+ *           (row 0 the initial state: teuk_extract_waveform before stepping,
+ *           then the rows teuk_step_n writes);
+ *   out_dev (nsteps + 1) x 10 doubles (device): dE/dt, dPx/dt, dPy/dt,
+ *           dPz/dt, dJz/dt, then E, Px, Py, Pz, Jz accumulated from t = 0 by
+ *           the trapezoidal rule (the recoil velocity is -P/M).
+ * The running integrals go into the caller's dev_workspace (ws_bytes, at
+ * least teuk_flux_workspace_size, 256-byte aligned).  Asynchronous on
+ * hip_stream. */
+typedef struct {
+    int32_t nmodes;
+    const int32_t* m;
+    const void* const* waves;
+    int64_t nsteps;
+    int32_t nth;
+    double dt;
+} teuk_flux_desc;
+
+int teuk_flux_workspace_size(const teuk_flux_desc* desc, size_t* bytes);
+int teuk_radiated_flux(const teuk_flux_desc* desc, void* hip_stream, void* dev_workspace, size_t ws_bytes,
+                       void* out_dev);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* teuk_last_error(void);
 

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libteuk.so")
 
-SOURCES = ["geometry.cpp", "stencil.hip", "block.hip", "batch_kernel.hip", "adjoint.hip", "static_ws.hip", "capi.cpp",
-           "batch.cpp", "orbit.cpp"]
+SOURCES = ["geometry.cpp", "stencil.hip", "block.hip", "batch_kernel.hip", "adjoint.hip", "static_ws.hip", "flux.hip",
+           "capi.cpp", "batch.cpp", "orbit.cpp"]
 
 # -ffp-contract=off: every fused multiply-add is written explicitly, so every
 # kernel variant rounds identically.  Packed FP32 instructions are disabled.

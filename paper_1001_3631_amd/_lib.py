@@ -65,6 +65,12 @@ class SourceDesc(ctypes.Structure):
                 ("orbit_dev", ctypes.c_void_p)]
 
 
+class FluxDesc(ctypes.Structure):
+    _fields_ = [("nmodes", ctypes.c_int32), ("m", ctypes.POINTER(ctypes.c_int32)),
+                ("waves", ctypes.POINTER(ctypes.c_void_p)), ("nsteps", ctypes.c_int64),
+                ("nth", ctypes.c_int32), ("dt", ctypes.c_double)]
+
+
 class WsRequest(ctypes.Structure):
     _fields_ = [("sigma_r_cells", ctypes.c_double), ("sigma_th_cells", ctypes.c_double),
                 ("cutoff_sigmas", ctypes.c_double), ("adjoint", ctypes.c_int32)]
@@ -137,6 +143,8 @@ SIGNATURES = {
     "teuk_set_kernel_timing": (ctypes.c_int, [_CTX, ctypes.c_int]),
     "teuk_kernel_timing": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),
+    "teuk_flux_workspace_size": (ctypes.c_int, [ctypes.POINTER(FluxDesc), ctypes.POINTER(ctypes.c_size_t)]),
+    "teuk_radiated_flux": (ctypes.c_int, [ctypes.POINTER(FluxDesc), _P, _P, ctypes.c_size_t, _P]),
     "teuk_last_error": (ctypes.c_char_p, []),
 }
 

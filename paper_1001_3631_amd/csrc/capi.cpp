@@ -1099,6 +1099,60 @@ int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, i
     return TEUK_OK;
 }
 
+static int check_flux(const teuk_flux_desc* d, size_t* h_bytes) {
+    if (d == nullptr) return fail(TEUK_EINVAL, "null flux descriptor");
+    if (d->nmodes < 1 || d->nmodes > teuk::kMaxFluxModes) return fail(TEUK_EINVAL, "need 1 <= nmodes <= 16");
+    if (d->m == nullptr || d->waves == nullptr) return fail(TEUK_EINVAL, "null m or waves array");
+    if (d->nsteps < 0 || d->nth < 3) return fail(TEUK_EINVAL, "need nsteps >= 0 and nth >= 3");
+    if (!(d->dt > 0.0)) return fail(TEUK_EINVAL, "need dt > 0");
+    for (int k = 0; k < d->nmodes; ++k) {
+        if (d->waves[k] == nullptr) return fail(TEUK_EINVAL, "null waveform " + std::to_string(k));
+        for (int l = 0; l < k; ++l)
+            if (d->m[l] == d->m[k]) return fail(TEUK_EINVAL, "the m of the waveforms must be distinct");
+    }
+    const size_t rows = static_cast<size_t>(d->nsteps) + 1;
+    *h_bytes = (sizeof(double2) * d->nmodes * rows * d->nth + 255) / 256 * 256;
+    return TEUK_OK;
+}
+
+int teuk_flux_workspace_size(const teuk_flux_desc* d, size_t* bytes) {
+    if (bytes == nullptr) return fail(TEUK_EINVAL, "null output");
+    *bytes = 0;
+    size_t hb = 0;
+    if (int rc = check_flux(d, &hb)) return rc;
+    *bytes = 2 * hb;     // H, then K
+    return TEUK_OK;
+}
+
+int teuk_radiated_flux(const teuk_flux_desc* d, void* hip_stream, void* ws, size_t ws_bytes, void* out) {
+    size_t hb = 0;
+    if (int rc = check_flux(d, &hb)) return rc;
+    if (out == nullptr) return fail(TEUK_EINVAL, "null output");
+    if (ws == nullptr || reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(TEUK_EINVAL, "the flux workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < 2 * hb)
+        return fail(TEUK_ENOMEM, "flux workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                     std::to_string(2 * hb));
+    teuk::FluxParams F;
+    F.nmodes = d->nmodes;
+    F.nth = d->nth;
+    F.rows = d->nsteps + 1;
+    F.half_dt = 0.5 * d->dt;
+    F.hth = M_PI / (d->nth - 1);
+    for (int k = 0; k < d->nmodes; ++k) {
+        F.waves[k] = static_cast<const double2*>(d->waves[k]);
+        F.m[k] = d->m[k];
+        F.next[k] = -1;
+        for (int l = 0; l < d->nmodes; ++l)
+            if (d->m[l] == d->m[k] + 1) F.next[k] = l;
+    }
+    F.H = static_cast<double2*>(ws);
+    F.K = reinterpret_cast<double2*>(static_cast<char*>(ws) + hb);
+    F.out = static_cast<double*>(out);
+    HIP_TRY(teuk::launch_flux(F, static_cast<hipStream_t>(hip_stream)), "flux kernels");
+    return TEUK_OK;
+}
+
 int teuk_set_kernel_timing(teuk_ctx* c, int enable) {
     if (int rc = check_ctx(c)) return rc;
     if (int rc = flush_timing(c)) return rc;

@@ -165,6 +165,22 @@ hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, in
 // Zero bytes (a multiple of 4) at p (16-byte aligned) on the stream.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 
+// Radiated fluxes of the extracted waves (flux.hip).
+constexpr int kMaxFluxModes = 16;
+struct FluxParams {
+    int nmodes = 0, nth = 0;
+    int64_t rows = 0;                       // time samples, t = n dt, n = 0 .. rows - 1
+    double half_dt = 0.0;
+    const double2* waves[kMaxFluxModes] = {};   // [rows][nth] each
+    int m[kMaxFluxModes] = {};
+    int next[kMaxFluxModes] = {};           // index of the mode with m + 1, or -1
+    double hth = 0.0;                       // theta_j = j hth
+    double2* H = nullptr;                   // [nmodes][rows][nth]
+    double2* K = nullptr;
+    double* out = nullptr;                  // [rows][10]
+};
+hipError_t launch_flux(const FluxParams& F, hipStream_t stream);
+
 // The library's static device workspace (static_ws.hip): its size, and its
 // device address on the current device (looked up once per device).
 constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;

@@ -446,3 +446,29 @@ class Batch:
         path = None if cache_path is None else os.fsencode(cache_path)
         L.check(self._lib.teuk_batch_autotune(self.ctx, path, table, cap, ctypes.byref(cnt)))
         return [(table[k].seg_rows, table[k].batch_mode, table[k].us_per_iteration) for k in range(cnt.value)]
+
+
+def radiated_flux(ms, waves, dt, stream=None):
+    """Radiated energy, linear and z angular momentum (teuk_radiated_flux).
+
+    ms: the m of each waveform; waves: complex128 device tensors of shape
+    (nsteps + 1, nth), row n = Phi at the extraction column at t = n dt (row
+    0 the initial state).  Returns a (nsteps + 1, 10) float64 device tensor:
+    dE/dt, dPx/dt, dPy/dt, dPz/dt, dJz/dt, E, Px, Py, Pz, Jz."""
+    lib = L.load()
+    n = len(ms)
+    rows, nth = waves[0].shape
+    for w in waves:
+        _need_device(w, (rows, nth), "waveform")
+    m_arr = (ctypes.c_int32 * n)(*[int(m) for m in ms])
+    p_arr = (ctypes.c_void_p * n)(*[w.data_ptr() for w in waves])
+    desc = L.FluxDesc(n, m_arr, p_arr, rows - 1, nth, float(dt))
+    nbytes = ctypes.c_size_t()
+    L.check(lib.teuk_flux_workspace_size(ctypes.byref(desc), ctypes.byref(nbytes)))
+    ws = device_buffer(nbytes.value)
+    out = torch.empty((rows, 10), dtype=torch.float64, device="cuda")
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    L.check(lib.teuk_radiated_flux(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream), _ptr(ws),
+                                   nbytes.value, _ptr(out)))
+    stream.synchronize()        # the workspace tensor goes out of scope here
+    return out

@@ -41,7 +41,16 @@ ADJOINT = dict(  # 3200 x 64, a = 0.7, 20000 steps, pulse + circular source, wav
     fd=dict(ndir=32, seed=44, h_rel=1e-3),
 )
 
-HBM_PLAIN = dict(  # forced EMRI physics on a 12800 x 256 grid (larger than the last-level cache)
+HBM_PLAIN = dict(  # forced EMRI physics on 25600 x 512: 420 MB per level, both levels 3.3x the 256 MB last-level cache
+    name="kerr_emri_25600x512",
+    grid=dict(M=1.0, a=0.9, s=-2, m=2, nr=25600, nth=512, rs_min=-200.0, rs_max=600.0, cfl=0.5,
+              rs_extract=500.0, ko_eps=KO_EPS),
+    steps=400,
+    pulse=None,
+    source=dict(r0=10.0, amplitude=1.0, sigma_r_cells=2.0, sigma_th_cells=2.0, cutoff_sigmas=8.0),
+)
+
+SCALE_GRID = dict(  # the 12800 x 256 grid of the 16-instance workload: 105 MB per level, inside the last-level cache
     name="kerr_emri_12800x256",
     grid=dict(M=1.0, a=0.9, s=-2, m=2, nr=12800, nth=256, rs_min=-200.0, rs_max=600.0, cfl=0.5,
               rs_extract=500.0, ko_eps=KO_EPS),
@@ -140,3 +149,23 @@ def fd_directions(nth, nr, ndir=32, seed=44):
 def random_state(nth, nr, seed):
     rng = np.random.default_rng(seed)
     return complex_normal(rng, (nth, nr)), complex_normal(rng, (nth, nr))
+
+
+def synthetic_waveforms(ms, nsteps, nth, dt, seed=6):
+    """Seeded smooth stand-ins for extracted waveforms of several m modes,
+    (nsteps + 1, nth) complex each: a few damped oscillations in t with
+    random amplitudes, frequencies and angular profiles (low powers of sin
+    and cos of theta_j = j pi/(nth - 1))."""
+    rng = np.random.default_rng(seed)
+    th = np.arange(nth) * np.pi / (nth - 1)
+    t = np.arange(nsteps + 1) * dt
+    out = []
+    for _ in ms:
+        w = np.zeros((nsteps + 1, nth), dtype=np.complex128)
+        for _ in range(3):
+            prof = sum(complex_normal(rng, ()) * np.sin(th) ** k * np.cos(th) ** l for k in range(3) for l in range(2))
+            om = rng.uniform(0.05, 0.6)
+            ga = rng.uniform(0.0, 0.02)
+            w += np.exp((-1j * om - ga) * t)[:, None] * prof[None, :]
+        out.append(w)
+    return out
