@@ -12,8 +12,12 @@ Also reported on the same JSON line:
                 launch (64 B per point: read u^n and write u^{n+k}, Phi and
                 Pi) over its average launch duration, from HIP events around
                 every stencil launch of one extra evolution;
-  hbm_grid      the same physics on 12800 x 256 (larger than the last-level
-                cache), GPts/s and algorithmic GB/s;
+  hbm_grid      the same physics on 25600 x 512 (both state levels 3.3x
+                the 256 MB last-level cache, so the traffic is HBM traffic):
+                GPts/s and a roofline block like the one above, with the
+                HBM bytes from counters when the committed counter summary
+                matches the current sources; beside it the achieved
+                bandwidth of a plain device copy (a STREAM-copy ceiling);
   batched       64 independent instances of uneven size (seeded m, a, grid
                 level, pulse centre), 10000 iterations each, in both batch
                 modes (one persistent launch per evolution captured in a HIP
@@ -25,8 +29,8 @@ Also reported on the same JSON line:
   adjoint_at_scale
                 16 instances on 12800 x 256 with eccentric orbits (seeded a,
                 m, p, e), forward + checkpointed adjoint one instance after
-                another (2000 iterations each by default; 50000 with
-                --scale-iterations 50000);
+                another, 50000 iterations each (snapshots every
+                ceil(sqrt N) iterations, every segment recomputed);
   cpu_baseline  the FP64 oracle on the host for a bounded number of
                 iterations of the same workload.
 """
@@ -43,15 +47,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 64.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lw_step_kernel_kerr_emri_6400x128_traffic.json")
 
 
-def measured_traffic(seg_rows, k_steps):
-    """HBM-side bytes per stencil launch from the committed counter summary,
-    or None if the stencil sources or the launch configuration changed since."""
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"lw_step_kernel_{workload}_traffic.json")
+
+
+def measured_traffic(workload, seg_rows, k_steps):
+    """Bytes leaving L2 per stencil launch from the committed counter summary
+    of this workload, or None if the stencil sources or the launch
+    configuration changed since."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
@@ -77,8 +85,11 @@ def parse():
     ap.add_argument("--batched-iterations", type=int, default=10000)
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the forward + checkpointed adjoint of the 16 instances on 12800 x 256")
-    ap.add_argument("--scale-iterations", type=int, default=2000,
-                    help="iterations per instance of that workload (its full length is 50000)")
+    ap.add_argument("--scale-iterations", type=int, default=None,
+                    help="iterations per instance of that workload (default its full 50000)")
+    ap.add_argument("--workload", default="kerr_emri_6400x128",
+                    choices=["kerr_emri_6400x128", "kerr_emri_25600x512"],
+                    help="main workload (the second one only for profiling passes)")
     ap.add_argument("--iterations", type=int, default=None,
                     help="override the iterations per evolution (profiling passes only)")
     ap.add_argument("--tuning", default=None,
@@ -100,6 +111,50 @@ def copy_calibration():
     print(json.dumps({"copy_calibration": {"kernel": "elementwise mul (torch)", "dispatches": 3,
                                            "read_bytes_per_dispatch": n * 16,
                                            "write_bytes_per_dispatch": n * 16}}), flush=True)
+
+
+def stream_copy():
+    """Achieved bandwidth of a plain device copy (read 1 GiB, write 1 GiB,
+    far beyond the last-level cache): the practical ceiling of a kernel that
+    streams its data once, timed with events over 20 launches."""
+    import torch
+    n = 64 * 1024 * 1024                      # complex128 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / 20
+    del a, b
+    return {"kernel": "device copy (torch copy_)", "bytes_per_launch": 2 * n * 16,
+            "avg_launch_us": round(s * 1e6, 1), "GBs": round(2 * n * 16 / s / 1e9, 1),
+            "frac_of_peak": round(2 * n * 16 / s / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def stencil_roofline(eng, workload, npts, run):
+    """Roofline block of the stencil: algorithmic bytes per launch (64 per
+    point) over the average launch duration from the launches' own events
+    during one more evolution (run()), plus the counter traffic if the
+    committed summary matches."""
+    tune = eng.tuning
+    eng.set_kernel_timing(True)
+    run()
+    kms, kn = eng.kernel_timing()
+    eng.set_kernel_timing(False)
+    avg_s = kms / kn * 1e-3
+    achieved = npts * BYTES_PER_POINT / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(workload, tune["seg_rows"], tune["k_steps"]),
+            "kernel": "lw_step_kernel" if tune["k_steps"] == 1 else "lw_block_kernel",
+            "avg_launch_us": round(avg_s * 1e6, 3),
+            "bytes_per_launch": int(npts * BYTES_PER_POINT), "launches_timed": kn,
+            "tuning": {"seg_rows": tune["seg_rows"], "k_steps": tune["k_steps"]}}
 
 
 def make_engine(cfg, nsteps):
@@ -222,8 +277,7 @@ def adjoint_at_scale(args):
         tf += t1 - t0
         tb += t2 - t1
         pts += g["nr"] * g["nth"] * n
-        interval = math.ceil(math.sqrt(n))
-        snap_bytes = max(snap_bytes, -(-n // interval) * 2 * g["nr"] * g["nth"] * 16)
+        snap_bytes = max(snap_bytes, eng.checkpoint_bytes(n, interval=0))
         peak_used = max(peak_used, free0 - free1)
         print(f"[bench] adjoint_at_scale instance {k}: a={g['a']:.3f} m={g['m']} p={o['p']:.2f} "
               f"e={o['e']:.3f} fwd {t1 - t0:.3f} s bwd {t2 - t1:.3f} s dA {dA:.6e}", file=sys.stderr,
@@ -231,14 +285,15 @@ def adjoint_at_scale(args):
         del gp, gq, gw, w, z
         eng.close()
     return {"workload": cfg["name"], "instances": cfg["instances"], "iterations": n,
+            "schedule": "instances one after another (each fills the GPU); snapshots every "
+                        "ceil(sqrt N) iterations, every segment recomputed in the backward",
             "tuning": tuning, "forward_s": round(tf, 3), "backward_with_recompute_s": round(tb, 3),
             "ratio_backward_over_forward": round(tb / tf, 3),
             "forward_gpts": round(pts / tf / 1e9, 3),
             "snapshot_bytes_per_instance": int(snap_bytes),
             "device_bytes_used_per_instance": int(peak_used),
-            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}"),
-            # 0 means no signal reached the extraction radius in this many
-            # iterations (then the dL/dA check above is empty)
+            # the check is empty (null) when no signal reached the extraction radius
+            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}") if w2_max > 0 else None,
             "waveform_norm2_max": float(f"{w2_max:.6e}")}
 
 
@@ -364,6 +419,52 @@ def all_m(args):
             "batched_over_plain": round(tp / tb, 3)}
 
 
+def hbm_grid():
+    """The stencil on a grid whose state lives in HBM (25600 x 512: both
+    levels 3.3x the last-level cache).  The single-step kernel at its best
+    segment length gives the roofline block (64 B per point update, HBM
+    bound); the autotuner's overall choice (which may fuse k iterations per
+    launch, 64/k B per point update) gives the throughput; a plain device
+    copy gives the achievable streaming bandwidth."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    hc = W.HBM_PLAIN
+    hg = hc["grid"]
+    hn = hc["steps"]
+    hpts = hg["nr"] * hg["nth"]
+    heng = make_engine(hc, hn)
+    table = heng.autotune(None)              # [(seg, k, us/iteration)], fastest first
+    best = table[0]
+    single = min((t for t in table if t[1] == 1), key=lambda t: t[2])
+    hphi = torch.zeros((hg["nth"], hg["nr"]), dtype=torch.complex128, device="cuda")
+    hpi = torch.zeros_like(hphi)
+    hwave = torch.empty((hn, hg["nth"]), dtype=torch.complex128, device="cuda")
+
+    def timed():
+        run_evolution(heng, hphi, hpi, hn, hwave)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_evolution(heng, hphi, hpi, hn, hwave)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1
+
+    out = {"workload": hc["name"], "iterations": hn, "state_bytes_per_level": hpts * 32}
+    heng.set_tuning(single[0], 1)
+    t_single = timed()
+    out["roofline"] = stencil_roofline(heng, hc["name"], hpts, lambda: run_evolution(heng, hphi, hpi, hn, hwave))
+    out["single_step_gpts"] = round(hn * hpts / t_single / 1e9, 3)
+    heng.set_tuning(best[0], best[1])
+    t_best = timed()
+    out["autotuned"] = {"tuning": {"seg_rows": best[0], "k_steps": best[1]},
+                        "gpts": round(hn * hpts / t_best / 1e9, 3),
+                        "effective_GBs": round(hn * hpts * BYTES_PER_POINT / t_best / 1e9, 1),
+                        "table_us_per_iteration": [[t[0], t[1], round(t[2], 2)] for t in table]}
+    heng.close()
+    del hphi, hpi, hwave
+    out["stream_copy"] = stream_copy()
+    return out
+
+
 def cpu_baseline(cfg, iters):
     import numpy as np
     from oracle import teuk_oracle as T
@@ -395,7 +496,7 @@ def main():
     from paper_1001_3631_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
-    cfg = W.KERR_EMRI
+    cfg = W.KERR_EMRI if args.workload == W.KERR_EMRI["name"] else W.HBM_PLAIN
     g = cfg["grid"]
     n = args.iterations or cfg["steps"]
     npts = g["nr"] * g["nth"]
@@ -425,48 +526,16 @@ def main():
           f"-> {gpts:.2f} GPts/s", file=sys.stderr, flush=True)
 
     # dominant kernel: average stencil launch duration from HIP events
-    eng.set_kernel_timing(True)
-    run_evolution(eng, zphi, zpi, n, wave)
-    kms, kn = eng.kernel_timing()
-    eng.set_kernel_timing(False)
-    avg_s = kms / kn * 1e-3
-    achieved = npts * BYTES_PER_POINT / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(tune["seg_rows"], tune["k_steps"]),
-                "kernel": "lw_step_kernel" if tune["k_steps"] == 1 else "lw_block_kernel",
-                "avg_launch_us": round(avg_s * 1e6, 3),
-                "bytes_per_launch": int(npts * BYTES_PER_POINT), "launches_timed": kn}
-    print(f"[bench] stencil launch avg {avg_s*1e6:.2f} us -> {achieved:.0f} GB/s algorithmic",
-          file=sys.stderr, flush=True)
+    roofline = stencil_roofline(eng, cfg["name"], npts, lambda: run_evolution(eng, zphi, zpi, n, wave))
+    print(f"[bench] stencil launch avg {roofline['avg_launch_us']:.2f} us -> {roofline['achieved']:.0f} GB/s "
+          f"algorithmic", file=sys.stderr, flush=True)
 
     extra = {}
-    if not args.no_hbm:
-        hc = W.HBM_PLAIN
-        hg = hc["grid"]
-        hn = hc["steps"]
-        heng = make_engine(hc, hn)
-        hphi = torch.zeros((hg["nth"], hg["nr"]), dtype=torch.complex128, device="cuda")
-        hpi = torch.zeros_like(hphi)
-        hwave = torch.empty((hn, hg["nth"]), dtype=torch.complex128, device="cuda")
-        run_evolution(heng, hphi, hpi, hn, hwave)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        run_evolution(heng, hphi, hpi, hn, hwave)
-        torch.cuda.synchronize()
-        he = time.perf_counter() - t1
-        heng.set_kernel_timing(True)
-        run_evolution(heng, hphi, hpi, hn, hwave)
-        hkms, hkn = heng.kernel_timing()
-        hpts = hg["nr"] * hg["nth"]
-        havg = hkms / hkn * 1e-3
-        extra["hbm_grid"] = {"workload": hc["name"], "iterations": hn,
-                             "gpts": round(hn * hpts / he / 1e9, 3),
-                             "kernel_avg_us": round(havg * 1e6, 2),
-                             "kernel_algorithmic_GBs": round(hpts * BYTES_PER_POINT / havg / 1e9, 1),
-                             "kernel_frac_of_peak": round(hpts * BYTES_PER_POINT / havg / 1e9 / HBM_PEAK_GBS, 4)}
-        print(f"[bench] {hc['name']}: {extra['hbm_grid']}", file=sys.stderr, flush=True)
-        heng.close()
+    if not args.no_hbm and cfg is not W.HBM_PLAIN:
+        eng.close()
+        del wave
+        extra["hbm_grid"] = hbm_grid()
+        print(f"[bench] hbm_grid: {extra['hbm_grid']}", file=sys.stderr, flush=True)
 
     if not args.no_adjoint:
         extra["adjoint"] = adjoint_ratio(args)

@@ -98,7 +98,7 @@ def test_block_straddling_a_source_batch(lead):
     assert_bitwise(got, ref)
 
 
-@pytest.mark.parametrize("cfg", [W.KERR_EMRI, W.HBM_PLAIN], ids=lambda c: c["name"])
+@pytest.mark.parametrize("cfg", [W.KERR_EMRI, W.SCALE_GRID], ids=lambda c: c["name"])
 def test_block_fullsize_bitwise(cfg):
     grid = cfg["grid"]
     ref = run(grid, None, None, [((8, 1), 24)], src_amp=1.0)
