@@ -26,6 +26,8 @@ Also reported on the same JSON line:
   all_m         every m (1..4) of one circular orbit on the 6400 x 128 grid,
                 each with its source, 4000 iterations as one batch, against
                 the same instances one after another;
+  small_batch   64 instances of the 801 x 33 grid, 2000 iterations, both
+                batch modes against the plain stepper (short launches);
   adjoint_at_scale
                 16 instances on 12800 x 256 with eccentric orbits (seeded a,
                 m, p, e), forward + checkpointed adjoint one instance after
@@ -360,6 +362,59 @@ def batched(args):
             "batched_over_plain": round(tp / tb, 3)}
 
 
+def small_batch(args):
+    """64 instances of the 801 x 33 Schwarzschild pulse grid (26 433 points
+    each), 2000 iterations, in both batch modes: a workload where one launch
+    per iteration is short, against the plain stepper one instance after
+    another."""
+    import torch
+    from paper_1001_3631_amd import workloads as W
+    from paper_1001_3631_amd.engine import Batch, Engine
+    cfg = W.SCHWARZSCHILD_PULSE
+    grids = [cfg["grid"]] * 64
+    n = cfg["steps"]
+    pts = sum(g["nr"] * g["nth"] for g in grids)
+    b = Batch(grids)
+    tune = b.autotune(None)
+    best_seg = {}
+    for seg, mode, _ in tune:
+        best_seg.setdefault(mode, seg)
+
+    def evolve():
+        for e in b.instances:
+            e.init_pulse(**cfg["pulse"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(n, waveform=False)
+        b.sync()
+        return time.perf_counter() - t0
+
+    names = {Batch.PERSISTENT: "persistent", Batch.PER_ITERATION: "per_iteration"}
+    times = {}
+    for mode in (Batch.PERSISTENT, Batch.PER_ITERATION):
+        b.set_tuning(best_seg[mode])
+        b.set_mode(mode)
+        evolve()
+        times[mode] = evolve()
+    b.close()
+    eng = Engine(**cfg["grid"])
+    eng.autotune(None)
+    eng.init_pulse(**cfg["pulse"])
+    eng.step(n, waveform=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(len(grids)):
+        eng.init_pulse(**cfg["pulse"])
+        eng.step(n, waveform=False)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t1
+    eng.close()
+    return {"workload": "64 x schwarzschild_pulse_801x33", "instances": len(grids), "points": pts, "iterations": n,
+            "by_mode": {names[m]: {"seg_rows": best_seg[m], "s": round(times[m], 3),
+                                   "gpts": round(pts * n / times[m] / 1e9, 3)} for m in times},
+            "plain_sequential_s": round(tp, 3), "plain_gpts": round(pts * n / tp / 1e9, 3)}
+
+
 def all_m(args):
     """Every m of one orbit (m = 1..4, each with the orbit's source) as one
     batch against the same instances stepped one after another."""
@@ -546,6 +601,8 @@ def main():
         print(f"[bench] batched: {extra['batched']}", file=sys.stderr, flush=True)
         extra["all_m"] = all_m(args)
         print(f"[bench] all_m: {extra['all_m']}", file=sys.stderr, flush=True)
+        extra["small_batch"] = small_batch(args)
+        print(f"[bench] small_batch: {extra['small_batch']}", file=sys.stderr, flush=True)
 
     if not args.no_scale:
         extra["adjoint_at_scale"] = adjoint_at_scale(args)

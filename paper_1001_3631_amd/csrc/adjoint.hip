@@ -76,11 +76,13 @@ __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
 
 // PART selects the waves a launch runs: 0 all of them; 1 those that meet no
 // source window; 2 those that do (its grid covers only the rectangle of
-// items near the windows, P.sub_*).  A launch of part 1 carries no source
-// bodies and so fits 248 VGPRs at seg 4 (two waves per SIMD, no spills),
-// where the kernel with all four bodies takes 264 (one wave per SIMD).
-// Parts 1 and 2 together run every wave once, each through the same body
-// as part 0, so the results are the same bits.
+// items near the windows, P.sub_*); 3 all of them without their source
+// terms (dL/dA then comes from adjoint_source_dA_kernel).  A launch of part 1
+// or 3 carries no source bodies and so fits 248 VGPRs at seg 4 (two waves
+// per SIMD, no spills), where the kernel with all four bodies takes 264 (one
+// wave per SIMD).  Parts 1 and 2 together run every wave once, each through
+// the same body as part 0; the source terms only add to dL/dA, so every
+// part gives lambda^n the same bits.
 template <int SEG, int PART>
 __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
     // rows jlo-4 .. jhi+5 (jhi - jlo <= SEG + 2).  Output row r needs mu rows
@@ -312,11 +314,12 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                           jlo >= 7 && jlo + SEG <= nth - 7;
     // (the launcher sets both window tables or neither)
     const int i0 = strip * 62 - 1;
-    const bool src = P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
+    // (part 3 treats every wave as one without source terms)
+    const bool src = PART != 3 && P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
                      (window_meets(org, false, P.win_r, P.win_t, i0, jlo, jhi - 1) ||
                       window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
     if (src) {   // uniform per wave
-        if constexpr (PART == 1) {
+        if constexpr (PART == 1 || PART == 3) {
             return;
         } else {
             if (interior)
@@ -340,6 +343,59 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
         if (lane == 0) P.dA_part[item] = v;
     }
+}
+
+// dL/dA of one reverse iteration from the source windows alone, for the
+// launches whose waves skip their source terms (part 3): the node part
+// sum_window dt Re(conj(mu_Pi) F_n) over the full step's window and the half
+// part sum_window (dt/2) Re(conj(lambda^h_Pi) F_h) over the half step's,
+// with mu and the half-level lambda formed by the same expressions as the
+// stencil's stages 2-4 (the host uses this only for windows whose rows stay
+// in [3, nth - 4], where no pole row folds into them).  Block b < win_t sums
+// node-window row b, block win_t + b half-window row b, one lane per column,
+// in a fixed tree; its sum replaces partial b of the iteration (part 3 wrote
+// zeros for every wave, and the partials are summed in a fixed order).
+__global__ void __launch_bounds__(64) adjoint_source_dA_kernel(AdjointParams P) {
+    const int4 org = *P.org;
+    const bool half = static_cast<int>(blockIdx.x) >= P.win_t;
+    const int dr = half ? blockIdx.x - P.win_t : blockIdx.x;
+    const int dc = threadIdx.x;
+    const double dt = P.dt, hdt = 0.5 * P.dt, inv_hr = P.inv_hr;
+    double v = 0.0;
+    if (dc < P.win_r) {
+        const int c = dr * P.win_r + dc;
+        if (!half) {
+            const int r = org.w + dr, i = org.z + dc;
+            if (r >= 1 && r <= P.nth - 2 && i >= 1 && i <= P.nr - 2)
+                v = dt * re_dot_conj(P.lam_pi[static_cast<size_t>(r) * P.ld + i], P.fn[c]);
+        } else {
+            const int r = org.y + dr, i = org.x + dc;
+            if (r >= 1 && r <= P.nth - 2 && i >= 0 && i <= P.nr - 2) {
+                const ThetaRow R = P.rows[r];
+                // stage 2/3 at nodes i and i + 1: Pi~ and dPi sources (zero off
+                // the interior columns), then stage 4's half-level lambda_Pi
+                double2 aq[2], dqv[2];
+                for (int t = 0; t < 2; ++t) {
+                    const int ii = i + t;
+                    double2 nq = cz(), ndq = cz();
+                    if (ii >= 1 && ii <= P.nr - 2) {
+                        const double2 p = P.lam_phi[static_cast<size_t>(r) * P.ld + ii];
+                        const double2 q = P.lam_pi[static_cast<size_t>(r) * P.ld + ii];
+                        const Coef cf = coef_at(load_rcol(P.rnode, P.nr, ii), R.cos_th, R.sin2, P.kerr != 0);
+                        const double2 ctq = cmul_conj(cf.ct, q);
+                        nq = make_double2(dt * (p.x - ctq.x), dt * (p.y - ctq.y));
+                        ndq = make_double2(dt * cf.b * q.x, dt * cf.b * q.y);
+                    }
+                    aq[t] = make_double2(0.5 * nq.x, 0.5 * nq.y);
+                    dqv[t] = make_double2(ndq.x * inv_hr, ndq.y * inv_hr);
+                }
+                const double2 hq = c_add(c_add(aq[0], dqv[0]), c_sub(aq[1], dqv[1]));
+                v = hdt * re_dot_conj(hq, P.fh[c]);
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
+    if (dc == 0) P.dA_part[blockIdx.x] = v;
 }
 
 // Sum n per-wave partials into *acc in a fixed order (the result depends only
@@ -401,7 +457,7 @@ bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
     return seg == 4 && nstrips * nseg > nsimd && nstrips <= INT16_MAX && nseg <= INT16_MAX;
 }
 
-hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream) {
+hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream, bool source_by_window) {
     const int items = P.nstrips * P.nseg;
     const dim3 grid((items + 3) / 4), block(256);
     // With a source on a grid of more waves than SIMDs, the waves without
@@ -411,7 +467,12 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
     const bool split = P.fh != nullptr && P.fn != nullptr && adjoint_splits(seg, P.nstrips, P.nseg, nsimd);
     switch (seg) {
         case 4:
-            if (split) {
+            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
+                // every wave without its source terms at two waves per SIMD,
+                // then dL/dA from the windows in one block
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 3>), grid, block, 0, stream, P, P.rows);
+                hipLaunchKernelGGL(adjoint_source_dA_kernel, dim3(2 * P.win_t), dim3(64), 0, stream, P);
+            } else if (split) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
                 const int sub = P.sub_ns * P.sub_ng;
                 if (sub > 0)

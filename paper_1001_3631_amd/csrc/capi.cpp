@@ -188,7 +188,8 @@ void set_tuning_fields(teuk_ctx* c, int seg, int k) {
 // same orbit samples, and widened by 2 cells against any difference in
 // rounding; the kernel still tests every wave itself.  ns or ng is 0 when
 // no item can meet them.
-void source_items(const teuk_ctx* c, int64_t m, int seg_rows, int nseg, int& s0, int& ns, int& g0, int& ng) {
+void source_items(const teuk_ctx* c, int64_t m, int seg_rows, int nseg, int& s0, int& ns, int& g0, int& ng,
+                  int& row_lo, int& row_hi) {
     const Geometry& G = c->G;
     const double* sh = c->h_orbit.data() + 3 * static_cast<size_t>(2 * m);
     const double* sn = c->h_orbit.data() + 3 * static_cast<size_t>(2 * m + 1);
@@ -219,6 +220,8 @@ void source_items(const teuk_ctx* c, int64_t m, int seg_rows, int nseg, int& s0,
     g0 = std::max(glo, 0);
     ns = slo < 0 ? 0 : shi - slo + 1;
     ng = glo < 0 ? 0 : ghi - glo + 1;
+    row_lo = r_lo;
+    row_hi = r_hi;
 }
 
 int flush_partials(teuk_ctx* c) {
@@ -683,6 +686,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
         if (int rc = flush_partials(c)) return rc;
         c->part_items = items;
     }
+    bool by_window = false;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t m = c->adj_clock - 1;
         P.fh = P.fn = nullptr;
@@ -695,13 +699,16 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
             P.fh = c->d_fh + slot * wsz;
             P.fn = c->d_fn + slot * wsz;
             P.org = c->d_org + slot;
+            by_window = false;
             if (teuk::adjoint_splits(c->adj_seg_rows, c->nstrips, c->adj_nseg, c->nsimd)) {
-                int s0, ns, g0, ng;
-                source_items(c, m, c->adj_seg_rows, c->adj_nseg, s0, ns, g0, ng);
+                int s0, ns, g0, ng, r_lo, r_hi;
+                source_items(c, m, c->adj_seg_rows, c->adj_nseg, s0, ns, g0, ng, r_lo, r_hi);
                 P.sub_s0 = static_cast<int16_t>(s0);
                 P.sub_ns = static_cast<int16_t>(ns);
                 P.sub_g0 = static_cast<int16_t>(g0);
                 P.sub_ng = static_cast<int16_t>(ng);
+                // rows [r_lo, r_hi) hold both windows with a 2-row margin
+                by_window = r_lo >= 3 && r_hi <= G.nth - 3;
             }
             if (c->part_filled == kPartSteps)
                 if (int rc = flush_partials(c)) return rc;
@@ -713,7 +720,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
         P.lam_pi = c->adj[c->adj_cur][1];
         P.out_phi = c->adj[c->adj_cur ^ 1][0];
         P.out_pi = c->adj[c->adj_cur ^ 1][1];
-        HIP_TRY(teuk::launch_adjoint(P, c->adj_seg_rows, c->nsimd, c->stream), "adjoint kernel");
+        HIP_TRY(teuk::launch_adjoint(P, c->adj_seg_rows, c->nsimd, c->stream, by_window), "adjoint kernel");
         c->adj_cur ^= 1;
         c->adj_clock = m;
     }

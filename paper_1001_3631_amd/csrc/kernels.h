@@ -136,7 +136,11 @@ hipError_t launch_add_region(double2* lam, int ld, const double2* src, int src_l
 bool valid_segment_rows(int seg);
 // nsimd: SIMDs of the device (a launch of more waves than that splits off
 // the source waves, see adjoint.hip).
-hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream);
+// source_by_window: the windows' rows stay in [3, nth - 4] (no pole folds
+// reach them), so a split launch may run every wave without source terms
+// and take dL/dA from the windows alone.
+hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream,
+                          bool source_by_window = false);
 // Whether launch_adjoint runs the waves near the source windows in a launch
 // of their own (then it reads P.sub_*).
 // (the rectangle of source items is held in 16-bit fields, hence the limits)

@@ -414,3 +414,34 @@ def test_adjoint_segment_setting():
         eng.set_tuning(8, 1, 5)
     assert eng.tuning == {"seg_rows": 4, "k_steps": 2, "adj_seg_rows": 16}
     eng.close()
+
+
+@pytest.mark.parametrize("th_cells", [None, 2.5, 124.5], ids=["equator", "near_theta0", "near_theta_pi"])
+def test_split_reverse_iteration_against_oracle(th_cells):
+    """On a grid of more adjoint waves than SIMDs (6400 x 128: 3328 waves at
+    segments of 4) the reverse iteration with a source is split: with the
+    windows away from the poles every wave runs without source terms and
+    dL/dA comes from the windows alone; with a window that reaches the pole
+    rows the waves near it run in a launch of their own.  Both against one
+    oracle reverse iteration on the same lambda, whole field and dL/dA; the
+    particle sits on the equator or two and a half cells from a pole (an
+    orbit table given to both sides)."""
+    grid = W.KERR_EMRI["grid"]
+    g = T.Grid(**grid)
+    n = 8
+    th_p = 0.5 * np.pi if th_cells is None else th_cells * g.hth
+    t = np.arange(2 * n + 1) * 0.5 * g.dt
+    rs_p = 12.7834
+    orbit = {"rs": np.full(t.shape, rs_p), "th": np.full(t.shape, th_p), "phi": 0.0307 * t}
+    eng = gpu_engine(grid)
+    eng.set_source(np.stack([orbit["rs"], orbit["th"], orbit["phi"]], axis=1), 1.0, 2.0, 2.0, 8.0)
+    src = T.Source(g, orbit, 1.0, 2.0, 2.0, 8.0)
+    lp, lq = W.random_state(g.nth, g.nr, seed=61)
+    m0 = n - 2
+    eng.adjoint_begin(m0, to_dev(lp), to_dev(lq))
+    eng.adjoint_step(1)
+    p1, q1, dA = eng.adjoint_get()
+    rp, rq, rdA = T.adjoint_step(g, lp, lq, m0 - 1, src)
+    e = (rel(host(p1), rp), rel(host(q1), rq), abs(dA - rdA) / abs(rdA))
+    print("split reverse iteration", th_cells, e)
+    assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
