@@ -226,28 +226,38 @@ def adjoint_ratio(args):
             "ratio_with_recompute": round((tc - tf) / tf, 3)}
 
 
+HBM_BYTES = 288e9          # MI355X HBM3E per GPU
+
+
 def adjoint_at_scale(args):
     """Forward + checkpointed adjoint of the 16 eccentric-orbit instances on
     12800 x 256 (seeded a, m, p, e, anomaly), one instance after another:
-    each alone fills the GPU (51200 waves per launch).  Per instance: the
-    orbit table, the forward keeping a snapshot every ceil(sqrt(N))
-    iterations, and the backward recomputing every segment from its snapshot
-    while sweeping it in reverse.  Loss sum |w - y|^2 against the waveform of
-    source amplitude 0.9 (zero initial data, so y = 0.9 w and dL/dA =
-    0.2 |w|^2 exactly: checked)."""
+    each alone fills the GPU (51200 waves per launch) and its state fits the
+    last-level cache.  Snapshots: the binomial schedule with the slots that
+    fit each instance's share of the HBM (288 GB / 16), i.e. the memory the
+    whole batch's snapshots could take if it were held at once; the backward
+    runs the schedule's recomputation (forced: this loss needs no forward
+    state) while sweeping in reverse.  Loss sum |w - y|^2 against the
+    waveform of source amplitude 0.9 (zero initial data, so y = 0.9 w and
+    dL/dA = 0.2 |w|^2 exactly: checked).  Also times the forward of all 16
+    instances as one batch (one launch per iteration over every instance)
+    against the same iterations one instance after another."""
     import torch
     from paper_1001_3631_amd import workloads as W
-    from paper_1001_3631_amd.engine import Engine
+    from paper_1001_3631_amd.engine import Batch, Engine, checkpoint_schedule
     cfg = W.ADJOINT_AT_SCALE
     n = args.scale_iterations or cfg["steps"]
     src = cfg["source"]
+    insts = W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])
+    budget = HBM_BYTES / len(insts)
     tf = tb = 0.0
     pts = 0
     worst_dA = 0.0
     snap_bytes = peak_used = 0
     w2_max = 0.0
     tuning = None
-    for k, inst in enumerate(W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])):
+    snapshots = None
+    for k, inst in enumerate(insts):
         g, o = inst["grid"], inst["orbit"]
         free0, _ = torch.cuda.mem_get_info()
         eng = Engine(**g)
@@ -257,13 +267,14 @@ def adjoint_at_scale(args):
         if tuning is None:
             eng.autotune(None)              # same shape for every instance: tune once (untimed)
             tuning = eng.tuning
+            snapshots = eng.snapshots_for_budget(n, budget)
         else:
             eng.set_tuning(tuning["seg_rows"], tuning["k_steps"])
         z = torch.zeros((g["nth"], g["nr"]), dtype=torch.complex128, device="cuda")
         eng.set_state(z, z)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        w, _ = eng.forward_checkpointed(n, interval=0, force_recompute=True)
+        w, _ = eng.forward_checkpointed(n, force_recompute=True, snapshots=snapshots)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         free1, _ = torch.cuda.mem_get_info()
@@ -279,24 +290,56 @@ def adjoint_at_scale(args):
         tf += t1 - t0
         tb += t2 - t1
         pts += g["nr"] * g["nth"] * n
-        snap_bytes = max(snap_bytes, eng.checkpoint_bytes(n, interval=0))
+        snap_bytes = max(snap_bytes, eng.checkpoint_bytes(n, snapshots=snapshots))
         peak_used = max(peak_used, free0 - free1)
         print(f"[bench] adjoint_at_scale instance {k}: a={g['a']:.3f} m={g['m']} p={o['p']:.2f} "
               f"e={o['e']:.3f} fwd {t1 - t0:.3f} s bwd {t2 - t1:.3f} s dA {dA:.6e}", file=sys.stderr,
               flush=True)
         del gp, gq, gw, w, z
         eng.close()
-    return {"workload": cfg["name"], "instances": cfg["instances"], "iterations": n,
-            "schedule": "instances one after another (each fills the GPU); snapshots every "
-                        "ceil(sqrt N) iterations, every segment recomputed in the backward",
-            "tuning": tuning, "forward_s": round(tf, 3), "backward_with_recompute_s": round(tb, 3),
-            "ratio_backward_over_forward": round(tb / tf, 3),
-            "forward_gpts": round(pts / tf / 1e9, 3),
-            "snapshot_bytes_per_instance": int(snap_bytes),
-            "device_bytes_used_per_instance": int(peak_used),
-            # the check is empty (null) when no signal reached the extraction radius
-            "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}") if w2_max > 0 else None,
-            "waveform_norm2_max": float(f"{w2_max:.6e}")}
+    _, _, (reps, recomputed, _) = checkpoint_schedule(n, snapshots)
+    out = {"workload": cfg["name"], "instances": cfg["instances"], "iterations": n,
+           "schedule": "instances one after another (each fills the GPU); binomial checkpoints, "
+                       "every recomputation of the schedule run in the backward",
+           "snapshots_per_instance": snapshots, "repetitions": reps,
+           "backward_recomputed_iterations": recomputed,
+           "snapshot_budget_bytes_per_instance": int(budget),
+           "tuning": tuning, "forward_s": round(tf, 3), "backward_with_recompute_s": round(tb, 3),
+           "ratio_backward_over_forward": round(tb / tf, 3),
+           "forward_gpts": round(pts / tf / 1e9, 3),
+           "snapshot_bytes_per_instance": int(snap_bytes),
+           "snapshot_bytes_all_instances": int(snap_bytes) * len(insts),
+           "device_bytes_used_per_instance": int(peak_used),
+           # the check is empty (null) when no signal reached the extraction radius
+           "dL_dA_worst_rel_vs_closed_form": float(f"{worst_dA:.3e}") if w2_max > 0 else None,
+           "waveform_norm2_max": float(f"{w2_max:.6e}")}
+
+    # the same 16 forwards as one batch (its fastest mode and segment length)
+    nb = min(n, 1000)
+    b = Batch([inst["grid"] for inst in insts])
+    for e, inst in zip(b.instances, insts):
+        o, g = inst["orbit"], inst["grid"]
+        orbit = e.orbit_eccentric(o["p"], o["e"], 2 * nb + 1, M=g["M"], a=g["a"], chi0=o["chi0"])
+        e.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
+    b.autotune(None)
+    zs = [torch.zeros(e.shape, dtype=torch.complex128, device="cuda") for e in b.instances]
+    for e, z0 in zip(b.instances, zs):
+        e.set_state(z0, z0)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(nb, waveform=False)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    mode = "persistent" if b.mode == Batch.PERSISTENT else "per_iteration"
+    seg = b.seg_rows
+    b.close()
+    out["batched_forward_probe"] = {
+        "iterations": nb, "mode": mode, "seg_rows": seg, "batch_s": round(t_batch, 3),
+        "batch_gpts": round(pts / n * nb / t_batch / 1e9, 3),
+        "one_after_another_gpts": out["forward_gpts"],
+        "batch_state_bytes": int(sum(2 * 2 * 16 * i["grid"]["nr"] * i["grid"]["nth"] for i in insts))}
+    return out
 
 
 def batched(args):

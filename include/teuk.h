@@ -238,17 +238,23 @@ int teuk_adjoint_get(teuk_ctx* ctx, void* lam_phi_dev, void* lam_pi_dev, double*
 /* ---- Checkpointed gradient -----------------------------------------------
  * A loss may depend on states the caller does not keep:
  *   L_s = state_weight * sum_{n = n_lo..n_hi} sum_{j0 <= j < j1, i0 <= i < i1} |Phi^n_ij|^2.
- * Its reverse sweep needs Phi^n at every n in [n_lo, n_hi], so the forward
- * keeps one snapshot of (Phi, Pi) every `interval` iterations (0 picks
- * ceil(sqrt(nsteps))) and the backward recomputes each segment from its
- * snapshot before sweeping it in reverse (memory: nsteps/interval
- * snapshots plus one segment of the rectangle).  With state_weight = 0 the
- * states are not needed; force_recompute != 0 recomputes the segments
- * anyway (same gradient, bitwise).  The iteration is linear, so its reverse
- * sweep needs no forward state, only the loss's own terms: one forward
- * recompute in all, whatever the interval, and the interval only trades
- * snapshot memory (nsteps/interval planes) against the rectangle buffer
- * (interval slots).
+ * Its reverse sweep needs Phi^n at every n in [n_lo, n_hi].  The iteration
+ * is linear, so the reverse sweep needs no other forward state.  Two
+ * schedules keep what it needs:
+ *   snapshots = 0 (uniform): the forward keeps one snapshot of (Phi, Pi)
+ *     every `interval` iterations (0 picks ceil(sqrt(nsteps))) and the
+ *     backward recomputes each segment from its snapshot once, keeping Phi
+ *     on the rectangle, before sweeping it in reverse.  One forward
+ *     recompute in all; memory nsteps/interval snapshots plus `interval`
+ *     copies of the rectangle.
+ *   snapshots = s >= 1 (binomial, for a memory budget): at most s snapshots
+ *     of (Phi, Pi) are held at any time, placed by the binomial schedule of
+ *     teuk_checkpoint_schedule (Griewank's revolve); reversing nsteps
+ *     iterations then recomputes r*nsteps - C(s + r, s + 1)
+ *     forward iterations, r the smallest number with C(s + r, s) >= nsteps.
+ *     `interval` must be 0.
+ * With state_weight = 0 the states are not needed; force_recompute != 0
+ * runs the schedule's recomputation anyway (same gradient, bitwise).
  *
  * The snapshots, the rectangle buffer and the loss's partial sums live in
  * the caller-owned device buffer ckpt_dev of ckpt_bytes bytes, 256-byte
@@ -269,6 +275,7 @@ int teuk_adjoint_get(teuk_ctx* ctx, void* lam_phi_dev, void* lam_pi_dev, double*
 typedef struct {
     int64_t nsteps;
     int64_t interval;
+    int64_t snapshots;
     double state_weight;
     int32_t i0, i1, j0, j1;
     int64_t n_lo, n_hi;
@@ -280,6 +287,23 @@ typedef struct {
 /* Bytes of checkpoint buffer (plan->ckpt_dev) the plan needs (host output);
  * ckpt_dev and ckpt_bytes are not read. */
 int teuk_checkpoint_size(const teuk_ctx* ctx, const teuk_grad_plan* plan, size_t* bytes);
+
+/* The binomial schedule for nsteps >= 1 iterations and snapshots >= 1
+ * slots (host only: needs no device or context).  phase 0 lists the
+ * forward's actions (from u^0 to u^nsteps), phase 1 the backward's (from
+ * u^nsteps down to reverse iteration 0), as triples (op, a, b) of int64:
+ *   op 0  advance a iterations from the current state, reaching iteration b;
+ *   op 1  store the current state u^b in slot a;
+ *   op 2  restore slot a, which holds u^b, into the current state;
+ *   op 3  reverse iteration a (lambda^{a+1} -> lambda^a) with the current
+ *         state at u^a.
+ * *count receives the number of actions of the phase; the first
+ * min(*count, cap) are written to actions (3 * cap int64, may be NULL with
+ * cap 0).  stats (may be NULL) receives {r, forward iterations recomputed by
+ * the backward, largest number of slots held at once}.  EINVAL for
+ * nsteps < 1, snapshots < 1 or phase not 0 or 1. */
+int teuk_checkpoint_schedule(int64_t nsteps, int64_t snapshots, int32_t phase, int64_t* actions, int64_t cap,
+                             int64_t* count, int64_t* stats);
 
 int teuk_forward_checkpointed(teuk_ctx* ctx, const teuk_grad_plan* plan, void* waveform_dev,
                               double* state_loss);

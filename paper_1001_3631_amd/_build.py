@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libteuk.so")
 
 SOURCES = ["geometry.cpp", "stencil.hip", "block.hip", "batch_kernel.hip", "adjoint.hip", "static_ws.hip", "flux.hip",
-           "capi.cpp", "batch.cpp", "orbit.cpp"]
+           "capi.cpp", "batch.cpp", "orbit.cpp", "revolve.cpp"]
 
 # -ffp-contract=off: every fused multiply-add is written explicitly, so every
 # kernel variant rounds identically.  Packed FP32 instructions are disabled.

@@ -77,7 +77,7 @@ class WsRequest(ctypes.Structure):
 
 
 class GradPlan(ctypes.Structure):
-    _fields_ = [("nsteps", ctypes.c_int64), ("interval", ctypes.c_int64),
+    _fields_ = [("nsteps", ctypes.c_int64), ("interval", ctypes.c_int64), ("snapshots", ctypes.c_int64),
                 ("state_weight", ctypes.c_double),
                 ("i0", ctypes.c_int32), ("i1", ctypes.c_int32), ("j0", ctypes.c_int32), ("j1", ctypes.c_int32),
                 ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64), ("force_recompute", ctypes.c_int32),
@@ -111,6 +111,9 @@ SIGNATURES = {
     "teuk_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, _P]),
     "teuk_extract_waveform": (ctypes.c_int, [_CTX, _P]),
     "teuk_checkpoint_size": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), ctypes.POINTER(ctypes.c_size_t)]),
+    "teuk_checkpoint_schedule": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "teuk_forward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P,
                                                  ctypes.POINTER(ctypes.c_double)]),
     "teuk_backward_checkpointed": (ctypes.c_int, [_CTX, ctypes.POINTER(GradPlan), _P, ctypes.c_double, _P, _P,

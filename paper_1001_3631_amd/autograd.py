@@ -48,20 +48,22 @@ def evolve(phi0, pi0, amplitude, engine, nsteps):
 
 
 class TeukEvolveCheckpointed(torch.autograd.Function):
-    """(w, L_s) = TeukEvolveCheckpointed.apply(phi0, pi0, amplitude, engine, nsteps, state_loss, interval).
+    """(w, L_s) = TeukEvolveCheckpointed.apply(phi0, pi0, amplitude, engine, nsteps, state_loss, interval,
+    snapshots).
 
     Like TeukEvolve, plus the state loss
     L_s = weight * sum_{n=n_lo..n_hi} sum_rect |Phi^n|^2 (state_loss dict), whose
     gradient needs the intermediate states: the forward keeps a snapshot every
     `interval` iterations (0 = ceil(sqrt(nsteps))) and the backward recomputes
-    each segment before sweeping it in reverse."""
+    each segment before sweeping it in reverse; or, with snapshots = s >= 1,
+    at most s snapshots placed by the binomial schedule."""
 
     @staticmethod
-    def forward(ctx, phi0, pi0, amplitude, engine, nsteps, state_loss, interval=0):
+    def forward(ctx, phi0, pi0, amplitude, engine, nsteps, state_loss, interval=0, snapshots=0):
         engine.set_state(phi0.detach().contiguous(), pi0.detach().contiguous())
         if engine.has_source:
             engine.set_amplitude(float(amplitude))
-        w, ls = engine.forward_checkpointed(int(nsteps), interval, state_loss)
+        w, ls = engine.forward_checkpointed(int(nsteps), interval, state_loss, snapshots=int(snapshots))
         ctx.engine = engine
         # the engine keeps the snapshots of its latest forward only
         ctx.generation = engine.checkpoint_generation
@@ -77,4 +79,4 @@ class TeukEvolveCheckpointed(torch.autograd.Function):
         dls = float(gls) if gls is not None else 0.0
         gp, gq, dA = eng.backward_checkpointed(gw, dls)
         gA = torch.tensor(dA, dtype=torch.float64, device=gp.device)
-        return gp, gq, gA, None, None, None, None
+        return gp, gq, gA, None, None, None, None, None

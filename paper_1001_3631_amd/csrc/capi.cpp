@@ -16,6 +16,7 @@
 #include "ctx.h"
 #include "geometry.h"
 #include "kernels.h"
+#include "revolve.h"
 
 using teuk::Geometry;
 using teuk::ThetaRow;
@@ -757,6 +758,9 @@ int teuk_adjoint_get(teuk_ctx* c, void* lam_phi, void* lam_pi, double* dL_dA) {
 static int check_plan(const teuk_ctx* c, const teuk_grad_plan* p, int64_t* interval) {
     if (p == nullptr) return fail(TEUK_EINVAL, "null plan");
     if (p->nsteps < 1) return fail(TEUK_EINVAL, "plan needs nsteps >= 1");
+    if (p->snapshots < 0) return fail(TEUK_EINVAL, "snapshots must be >= 0");
+    if (p->snapshots > 0 && p->interval != 0)
+        return fail(TEUK_EINVAL, "a binomial plan (snapshots > 0) takes interval 0");
     int64_t iv = p->interval;
     if (iv == 0) iv = static_cast<int64_t>(std::ceil(std::sqrt(static_cast<double>(p->nsteps))));
     if (iv < 1) return fail(TEUK_EINVAL, "interval must be >= 0");
@@ -773,8 +777,10 @@ static int check_plan(const teuk_ctx* c, const teuk_grad_plan* p, int64_t* inter
 
 namespace {
 
-// Byte offsets inside a plan's checkpoint buffer: 2K snapshot planes, then
-// (state loss only) the rectangle buffer, the loss sum and its partials.
+// Byte offsets inside a plan's checkpoint buffer: 2K snapshot planes (K =
+// the uniform schedule's snapshot count, or the binomial schedule's slots),
+// then (state loss only) the rectangle buffer (uniform schedule only), the
+// loss sum and its partials.
 struct CkptLayout {
     size_t snaps = 0, seg = 0, ls = 0, ls_part = 0, total = 0;
 };
@@ -788,11 +794,12 @@ CkptLayout ckpt_layout(const teuk_ctx* c, const teuk_grad_plan* p, int64_t iv) {
         return at;
     };
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
-    const int64_t K = (p->nsteps + iv - 1) / iv;
+    const bool binomial = p->snapshots > 0;
+    const int64_t K = binomial ? p->snapshots : (p->nsteps + iv - 1) / iv;
     L.snaps = take(2 * static_cast<size_t>(K) * plane_bytes);
     if (p->state_weight != 0.0) {
         const size_t wr = static_cast<size_t>(p->i1 - p->i0), hr = static_cast<size_t>(p->j1 - p->j0);
-        L.seg = take(sizeof(double2) * wr * hr * static_cast<size_t>(iv));
+        L.seg = take(binomial ? 0 : sizeof(double2) * wr * hr * static_cast<size_t>(iv));
         L.ls = take(sizeof(double));
         L.ls_part = take(sizeof(double) * (c->G.nth + teuk::reduce_partials_blocks(c->G.nth)));
     }
@@ -814,10 +821,193 @@ int bind_ckpt(teuk_ctx* c, const teuk_grad_plan* p, int64_t iv) {
     char* base = static_cast<char*>(p->ckpt_dev);
     c->snaps = reinterpret_cast<double2*>(base + L.snaps);
     const bool sl = p->state_weight != 0.0;
-    c->seg_buf = sl ? reinterpret_cast<double2*>(base + L.seg) : nullptr;
+    c->seg_buf = (sl && p->snapshots == 0) ? reinterpret_cast<double2*>(base + L.seg) : nullptr;
     c->d_ls = sl ? reinterpret_cast<double*>(base + L.ls) : nullptr;
     c->d_ls_part = sl ? reinterpret_cast<double*>(base + L.ls_part) : nullptr;
     return TEUK_OK;
+}
+
+}  // namespace
+
+int teuk_checkpoint_schedule(int64_t nsteps, int64_t snapshots, int32_t phase, int64_t* actions, int64_t cap,
+                             int64_t* count, int64_t* stats) {
+    if (count == nullptr) return fail(TEUK_EINVAL, "null count");
+    *count = 0;
+    if (nsteps < 1 || snapshots < 1) return fail(TEUK_EINVAL, "need nsteps >= 1 and snapshots >= 1");
+    if (phase != 0 && phase != 1) return fail(TEUK_EINVAL, "phase must be 0 (forward) or 1 (backward)");
+    if (cap < 0 || (cap > 0 && actions == nullptr)) return fail(TEUK_EINVAL, "bad action buffer");
+    teuk_detail::RevolveSchedule S;
+    if (!teuk_detail::revolve_schedule(nsteps, snapshots, &S)) return fail(TEUK_EINVAL, "no schedule");
+    const auto& list = phase == 0 ? S.forward : S.backward;
+    *count = static_cast<int64_t>(list.size());
+    const int64_t n = std::min<int64_t>(cap, *count);
+    for (int64_t k = 0; k < n; ++k) {
+        actions[3 * k] = list[k].op;
+        actions[3 * k + 1] = list[k].a;
+        actions[3 * k + 2] = list[k].b;
+    }
+    if (stats != nullptr) {
+        stats[0] = S.repetitions;
+        stats[1] = S.backward_advances;
+        stats[2] = S.slots_used;
+    }
+    return TEUK_OK;
+}
+
+namespace {
+
+// Copy the current state into snapshot slot k, or back.
+int snapshot_copy(teuk_ctx* c, int64_t k, bool restore) {
+    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+    const size_t plane_elems = plane_bytes / sizeof(double2);
+    for (int f = 0; f < 2; ++f) {
+        double2* snap = c->snaps + (2 * k + f) * plane_elems;
+        double2* cur = c->plane[c->cur][f];
+        HIP_TRY(hipMemcpyAsync(restore ? cur : snap, restore ? snap : cur, plane_bytes, hipMemcpyDeviceToDevice,
+                               c->stream), restore ? "restore" : "snapshot");
+    }
+    return TEUK_OK;
+}
+
+// Add |Phi^n|^2 on the plan's rectangle to the loss sum (phi: the Phi plane
+// holding u^n).
+int accumulate_state_loss(teuk_ctx* c, const teuk_grad_plan* p, const double2* phi) {
+    HIP_TRY(teuk::launch_region_sumsq(phi, c->ld, p->i0, p->i1, p->j0, p->j1, c->d_ls_part, c->stream),
+            "state loss");
+    HIP_TRY(teuk::launch_reduce_partials(c->d_ls_part, p->j1 - p->j0, c->d_ls_part + c->G.nth, c->d_ls,
+                                         c->stream), "state loss reduction");
+    return TEUK_OK;
+}
+
+// Runs the actions of a binomial schedule.  The current state may live in a
+// snapshot slot: a restore only names the slot, the next iteration reads its
+// input from there, and the iteration that precedes a store writes its
+// output straight into the slot, so no state is copied except the caller's
+// u^0 (and, at the end, the last state back into the context's level).
+struct RevolveRunner {
+    teuk_ctx* c;
+    const teuk_grad_plan* p;
+    size_t plane_elems;
+    int64_t src = -1;   // slot holding the current state; -1: the context's current level
+
+    double2* slot_plane(int64_t k, int f) const { return c->snaps + (2 * k + f) * plane_elems; }
+    double2* cur_phi() const { return src >= 0 ? slot_plane(src, 0) : c->plane[c->cur][0]; }
+
+    // One iteration from the current state, its output into slot to_slot
+    // (-1: the context's other level).
+    int step_once(int64_t to_slot, double2* wave) {
+        double2* saved[2][2];
+        std::memcpy(saved, c->plane, sizeof(saved));
+        const int r = c->cur, w = c->cur ^ 1;
+        for (int f = 0; f < 2; ++f) {
+            if (src >= 0) c->plane[r][f] = slot_plane(src, f);
+            if (to_slot >= 0) c->plane[w][f] = slot_plane(to_slot, f);
+        }
+        const int rc = teuk_step_n(c, 1, wave);
+        std::memcpy(c->plane, saved, sizeof(saved));
+        if (rc) return rc;
+        src = to_slot;
+        return TEUK_OK;
+    }
+
+    // k iterations; store_slot >= 0: the last one writes into that slot.
+    // with_loss: accumulate the state loss over the plan's window.
+    int advance(int64_t k, int64_t store_slot, double2* wave, bool with_loss) {
+        const int nth = c->G.nth;
+        int64_t done = 0;
+        while (done < k) {
+            const int64_t n = c->steps_done;
+            const bool last = done == k - 1;
+            const bool in_win = with_loss && n + 1 >= p->n_lo && n + 1 <= p->n_hi;
+            if (src >= 0 || (last && store_slot >= 0) || in_win) {
+                if (int rc = step_once(last ? store_slot : -1, wave ? wave + n * nth : nullptr)) return rc;
+                done += 1;
+                if (in_win)
+                    if (int rc = accumulate_state_loss(c, p, cur_phi())) return rc;
+                continue;
+            }
+            int64_t run = k - done - (store_slot >= 0 ? 1 : 0);
+            if (with_loss && n + 1 < p->n_lo) run = std::min(run, p->n_lo - 1 - n);
+            if (int rc = teuk_step_n(c, run, wave ? wave + n * nth : nullptr)) return rc;
+            done += run;
+        }
+        return TEUK_OK;
+    }
+
+    // Copy the current state into slot k (only the caller's u^0 needs this).
+    int store_copy(int64_t k) {
+        const size_t plane_bytes = plane_elems * sizeof(double2);
+        for (int f = 0; f < 2; ++f) {
+            const double2* from = src >= 0 ? slot_plane(src, f) : c->plane[c->cur][f];
+            HIP_TRY(hipMemcpyAsync(slot_plane(k, f), from, plane_bytes, hipMemcpyDeviceToDevice, c->stream),
+                    "snapshot");
+        }
+        src = k;
+        return TEUK_OK;
+    }
+
+    // Leave the current state in the context's level.
+    int materialize() {
+        if (src < 0) return TEUK_OK;
+        const size_t plane_bytes = plane_elems * sizeof(double2);
+        for (int f = 0; f < 2; ++f)
+            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][f], slot_plane(src, f), plane_bytes, hipMemcpyDeviceToDevice,
+                                   c->stream), "restore");
+        src = -1;
+        return TEUK_OK;
+    }
+
+    int run(const std::vector<teuk_detail::RevolveAction>& acts, double2* wave, bool with_loss, const void* gw,
+            double scale) {
+        const bool sl = p->state_weight != 0.0;
+        for (size_t i = 0; i < acts.size(); ++i) {
+            const auto& act = acts[i];
+            switch (act.op) {
+                case teuk_detail::kAdvance: {
+                    // a store right after an advance takes the advance's last output
+                    const bool then_store = i + 1 < acts.size() && acts[i + 1].op == teuk_detail::kStore;
+                    if (int rc = advance(act.a, then_store ? acts[i + 1].a : -1, wave, with_loss)) return rc;
+                    if (then_store) ++i;
+                    break;
+                }
+                case teuk_detail::kStore:
+                    if (int rc = store_copy(act.a)) return rc;
+                    break;
+                case teuk_detail::kRestore:
+                    src = act.a;
+                    c->steps_done = act.b;
+                    break;
+                default: {
+                    const int64_t m = act.a;
+                    if (c->steps_done != m || c->adj_clock != m + 1)
+                        return fail(TEUK_ESTATE, "checkpoint schedule out of order");
+                    if (int rc = teuk_adjoint_step_n(c, 1, gw)) return rc;
+                    if (sl && m >= 1 && m >= p->n_lo && m <= p->n_hi)
+                        HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld, cur_phi(), c->ld, false,
+                                                        scale, p->i0, p->i1, p->j0, p->j1, c->stream),
+                                "state grad");
+                }
+            }
+        }
+        return materialize();
+    }
+};
+
+// Forward of a binomial plan: the schedule's stores on the way to u^nsteps.
+int forward_binomial(teuk_ctx* c, const teuk_grad_plan* p, double2* wave) {
+    teuk_detail::RevolveSchedule S;
+    if (!teuk_detail::revolve_schedule(p->nsteps, p->snapshots, &S)) return fail(TEUK_EINVAL, "no schedule");
+    RevolveRunner R{c, p, static_cast<size_t>(c->ld) * c->G.nth};
+    return R.run(S.forward, wave, p->state_weight != 0.0, nullptr, 0.0);
+}
+
+// Backward of a binomial plan from u^nsteps: restores, recomputes and
+// reverse iterations in the schedule's order.
+int backward_binomial(teuk_ctx* c, const teuk_grad_plan* p, const void* gw, double scale) {
+    teuk_detail::RevolveSchedule S;
+    if (!teuk_detail::revolve_schedule(p->nsteps, p->snapshots, &S)) return fail(TEUK_EINVAL, "no schedule");
+    RevolveRunner R{c, p, static_cast<size_t>(c->ld) * c->G.nth};
+    return R.run(S.backward, nullptr, false, gw, scale);
 }
 
 }  // namespace
@@ -841,31 +1031,25 @@ int teuk_forward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, void* wav
     if (int rc = bind_ckpt(c, plan, iv)) return rc;
     const Geometry& G = c->G;
     const int64_t N = plan->nsteps;
-    const int64_t K = (N + iv - 1) / iv;
-    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    const size_t plane_elems = plane_bytes / sizeof(double2);
     const bool sl = plan->state_weight != 0.0;
     if (sl) HIP_TRY(teuk::launch_zero(c->d_ls, sizeof(double), c->stream), "state loss zero");
     double2* wave = static_cast<double2*>(waveform);
-    for (int64_t k = 0; k < K; ++k) {
-        const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
-        HIP_TRY(hipMemcpyAsync(c->snaps + (2 * k) * plane_elems, c->plane[c->cur][0], plane_bytes,
-                               hipMemcpyDeviceToDevice, c->stream), "snapshot");
-        HIP_TRY(hipMemcpyAsync(c->snaps + (2 * k + 1) * plane_elems, c->plane[c->cur][1], plane_bytes,
-                               hipMemcpyDeviceToDevice, c->stream), "snapshot");
-        const bool touches = sl && !(s1 < plan->n_lo || s0 + 1 > plan->n_hi);
-        if (!touches) {
-            if (int rc = teuk_step_n(c, s1 - s0, wave ? wave + s0 * G.nth : nullptr)) return rc;
-            continue;
-        }
-        for (int64_t n = s0; n < s1; ++n) {
-            if (int rc = teuk_step_n(c, 1, wave ? wave + n * G.nth : nullptr)) return rc;
-            if (n + 1 >= plan->n_lo && n + 1 <= plan->n_hi) {
-                HIP_TRY(teuk::launch_region_sumsq(c->plane[c->cur][0], c->ld, plan->i0, plan->i1, plan->j0,
-                                                  plan->j1, c->d_ls_part, c->stream), "state loss");
-                HIP_TRY(teuk::launch_reduce_partials(c->d_ls_part, plan->j1 - plan->j0, c->d_ls_part + G.nth,
-                                                     c->d_ls, c->stream),
-                        "state loss reduction");
+    if (plan->snapshots > 0) {
+        if (int rc = forward_binomial(c, plan, wave)) return rc;
+    } else {
+        const int64_t K = (N + iv - 1) / iv;
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
+            if (int rc = snapshot_copy(c, k, false)) return rc;
+            const bool touches = sl && !(s1 < plan->n_lo || s0 + 1 > plan->n_hi);
+            if (!touches) {
+                if (int rc = teuk_step_n(c, s1 - s0, wave ? wave + s0 * G.nth : nullptr)) return rc;
+                continue;
+            }
+            for (int64_t n = s0; n < s1; ++n) {
+                if (int rc = teuk_step_n(c, 1, wave ? wave + n * G.nth : nullptr)) return rc;
+                if (n + 1 >= plan->n_lo && n + 1 <= plan->n_hi)
+                    if (int rc = accumulate_state_loss(c, plan, c->plane[c->cur][0])) return rc;
             }
         }
     }
@@ -890,27 +1074,26 @@ int teuk_backward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, const vo
     if (!c->ckpt_valid || std::memcmp(&c->ckpt_plan, plan, sizeof(teuk_grad_plan)) != 0 ||
         c->steps_done != plan->nsteps)
         return fail(TEUK_ESTATE, "run teuk_forward_checkpointed with the same plan first");
-    const Geometry& G = c->G;
     const int64_t N = plan->nsteps;
-    const int64_t K = (N + iv - 1) / iv;
     const bool sl = plan->state_weight != 0.0;
     const bool recompute = sl || plan->force_recompute != 0;
     const double scale = 2.0 * plan->state_weight * dL_dLs;
     const int wr = plan->i1 - plan->i0, hr = plan->j1 - plan->j0;
-    const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
-    const size_t plane_elems = plane_bytes / sizeof(double2);
     if (int rc = teuk_adjoint_begin(c, nullptr, nullptr, N, gw)) return rc;
     if (sl && N >= plan->n_lo && N <= plan->n_hi)
         HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld, c->plane[c->cur][0], c->ld, false, scale,
                                         plan->i0, plan->i1, plan->j0, plan->j1, c->stream), "state grad");
-    for (int64_t k = K - 1; k >= 0; --k) {
-        const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
-        if (recompute) {
+    if (!recompute) {
+        // the reverse sweep needs no forward state
+        if (int rc = teuk_adjoint_step_n(c, N, gw)) return rc;
+    } else if (plan->snapshots > 0) {
+        if (int rc = backward_binomial(c, plan, gw, scale)) return rc;
+    } else {
+        const int64_t K = (N + iv - 1) / iv;
+        for (int64_t k = K - 1; k >= 0; --k) {
+            const int64_t s0 = k * iv, s1 = std::min(s0 + iv, N);
             // restore u^{s0} and recompute the segment, keeping Phi on the rectangle
-            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][0], c->snaps + (2 * k) * plane_elems, plane_bytes,
-                                   hipMemcpyDeviceToDevice, c->stream), "restore");
-            HIP_TRY(hipMemcpyAsync(c->plane[c->cur][1], c->snaps + (2 * k + 1) * plane_elems, plane_bytes,
-                                   hipMemcpyDeviceToDevice, c->stream), "restore");
+            if (int rc = snapshot_copy(c, k, true)) return rc;
             c->steps_done = s0;
             for (int64_t m = s0; m < s1; ++m) {
                 if (sl && m >= plan->n_lo && m <= plan->n_hi)
@@ -922,14 +1105,14 @@ int teuk_backward_checkpointed(teuk_ctx* c, const teuk_grad_plan* plan, const vo
                 if (m + 1 < s1)
                     if (int rc = teuk_step_n(c, 1, nullptr)) return rc;
             }
-        }
-        for (int64_t m = s1 - 1; m >= s0; --m) {
-            if (int rc = teuk_adjoint_step_n(c, 1, gw)) return rc;
-            if (sl && m >= 1 && m >= plan->n_lo && m <= plan->n_hi)
-                HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld,
-                                                c->seg_buf + static_cast<size_t>(m - s0) * wr * hr, wr, true,
-                                                scale, plan->i0, plan->i1, plan->j0, plan->j1, c->stream),
-                        "state grad");
+            for (int64_t m = s1 - 1; m >= s0; --m) {
+                if (int rc = teuk_adjoint_step_n(c, 1, gw)) return rc;
+                if (sl && m >= 1 && m >= plan->n_lo && m <= plan->n_hi)
+                    HIP_TRY(teuk::launch_add_region(c->adj[c->adj_cur][0], c->ld,
+                                                    c->seg_buf + static_cast<size_t>(m - s0) * wr * hr, wr, true,
+                                                    scale, plan->i0, plan->i1, plan->j0, plan->j1, c->stream),
+                            "state grad");
+            }
         }
     }
     c->ckpt_valid = false;

@@ -274,12 +274,16 @@ class Engine:
         return p, q, (dA.value if want_dA else None)
 
     # -- checkpointed gradient ----------------------------------------------
-    def _plan(self, nsteps, interval, state_loss, force_recompute):
+    def _make_plan(self, nsteps, interval, state_loss, force_recompute, snapshots):
         sl = state_loss or {}
-        plan = L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
-                          int(sl.get("i0", 0)), int(sl.get("i1", 0)), int(sl.get("j0", 0)),
-                          int(sl.get("j1", 0)), int(sl.get("n_lo", 0)), int(sl.get("n_hi", 0)),
-                          1 if force_recompute else 0, None, 0)
+        return L.GradPlan(nsteps=int(nsteps), interval=int(interval), snapshots=int(snapshots),
+                          state_weight=float(sl.get("weight", 0.0)),
+                          i0=int(sl.get("i0", 0)), i1=int(sl.get("i1", 0)), j0=int(sl.get("j0", 0)),
+                          j1=int(sl.get("j1", 0)), n_lo=int(sl.get("n_lo", 0)), n_hi=int(sl.get("n_hi", 0)),
+                          force_recompute=1 if force_recompute else 0, ckpt_dev=None, ckpt_bytes=0)
+
+    def _plan(self, nsteps, interval, state_loss, force_recompute, snapshots):
+        plan = self._make_plan(nsteps, interval, state_loss, force_recompute, snapshots)
         nbytes = ctypes.c_size_t()
         L.check(self._lib.teuk_checkpoint_size(self.ctx, ctypes.byref(plan), ctypes.byref(nbytes)))
         if self._ckpt_buf is None or self._ckpt_buf.numel() < nbytes.value:
@@ -289,22 +293,29 @@ class Engine:
         plan.ckpt_bytes = self._ckpt_buf.numel()
         return plan
 
-    def checkpoint_bytes(self, nsteps, interval=0, state_loss=None):
-        """Bytes of checkpoint buffer a checkpointed run of nsteps needs."""
-        sl = state_loss or {}
-        plan = L.GradPlan(int(nsteps), int(interval), float(sl.get("weight", 0.0)),
-                          int(sl.get("i0", 0)), int(sl.get("i1", 0)), int(sl.get("j0", 0)),
-                          int(sl.get("j1", 0)), int(sl.get("n_lo", 0)), int(sl.get("n_hi", 0)), 0, None, 0)
+    def checkpoint_bytes(self, nsteps, interval=0, state_loss=None, snapshots=0):
+        """Bytes of checkpoint buffer a checkpointed run of nsteps needs
+        (uniform schedule, or binomial with `snapshots` slots)."""
+        plan = self._make_plan(nsteps, interval, state_loss, False, snapshots)
         nbytes = ctypes.c_size_t()
         L.check(self._lib.teuk_checkpoint_size(self.ctx, ctypes.byref(plan), ctypes.byref(nbytes)))
         return nbytes.value
 
-    def forward_checkpointed(self, nsteps, interval=0, state_loss=None, force_recompute=False):
+    def snapshots_for_budget(self, nsteps, budget_bytes, state_loss=None):
+        """The most binomial snapshot slots whose checkpoint buffer fits
+        budget_bytes (at least 1), capped at nsteps."""
+        one = self.checkpoint_bytes(nsteps, state_loss=state_loss, snapshots=1)
+        per = self.checkpoint_bytes(nsteps, state_loss=state_loss, snapshots=2) - one
+        return int(max(1, min(int(nsteps), 1 + (int(budget_bytes) - one) // per)))
+
+    def forward_checkpointed(self, nsteps, interval=0, state_loss=None, force_recompute=False, snapshots=0):
         """Run nsteps iterations keeping snapshots for the reverse sweep.
         state_loss: dict(weight, i0, i1, j0, j1, n_lo, n_hi) for
         L_s = weight * sum_{n=n_lo..n_hi} sum_rect |Phi^n|^2, or None.
+        snapshots 0: a snapshot every `interval` iterations (0: ceil(sqrt));
+        snapshots s >= 1: the binomial schedule with at most s snapshots.
         Returns (waveform, L_s)."""
-        self._ckpt = self._plan(nsteps, interval, state_loss, force_recompute)
+        self._ckpt = self._plan(nsteps, interval, state_loss, force_recompute, snapshots)
         self.checkpoint_generation += 1
         nth = self.shape[0]
         w = torch.empty((int(nsteps), nth), dtype=torch.complex128, device="cuda")
@@ -472,3 +483,24 @@ def radiated_flux(ms, waves, dt, stream=None):
                                    nbytes.value, _ptr(out)))
     stream.synchronize()        # the workspace tensor goes out of scope here
     return out
+
+
+def checkpoint_schedule(nsteps, snapshots):
+    """The binomial checkpoint schedule (host only): (forward actions,
+    backward actions, stats).  Actions are (op, a, b) rows: 0 advance a
+    iterations to iteration b, 1 store u^b in slot a, 2 restore slot a
+    (u^b), 3 reverse iteration a; stats = (repetitions, iterations
+    recomputed by the backward, most slots held at once)."""
+    import numpy as np
+    lib = L.load()
+    out = []
+    stats = (ctypes.c_int64 * 3)()
+    for phase in (0, 1):
+        count = ctypes.c_int64()
+        L.check(lib.teuk_checkpoint_schedule(int(nsteps), int(snapshots), phase, None, 0, ctypes.byref(count), None))
+        buf = np.zeros((max(count.value, 1), 3), dtype=np.int64)
+        L.check(lib.teuk_checkpoint_schedule(int(nsteps), int(snapshots), phase,
+                                             buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), count.value,
+                                             ctypes.byref(count), stats))
+        out.append(buf[:count.value])
+    return out[0], out[1], tuple(int(x) for x in stats)

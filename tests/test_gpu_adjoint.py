@@ -2,6 +2,8 @@
 the dot-product identity, central differences of the GPU forward, and the
 torch.autograd wrapper."""
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -248,6 +250,59 @@ def test_checkpoint_recompute_equals_residual_only_bitwise():
         assert torch.equal(w2, w)
         gp, gq, dA = eng.backward_checkpointed(gw)
         assert torch.equal(gp, gp0) and torch.equal(gq, gq0) and dA == dA0
+
+
+@pytest.mark.parametrize("snapshots", [1, 2, 3, 6, 200])
+def test_binomial_schedule_gradient_equals_uniform_bitwise(snapshots):
+    """The binomial schedule runs the same reverse iterations with the same
+    forward states as the uniform one, only recomputed in another order: the
+    state loss, the waveform and every gradient are bitwise equal, from one
+    slot (every reverse iteration restarts at u^0) to more slots than
+    iterations."""
+    grid, n = _adjoint_case(90)
+    g = T.Grid(**grid)
+    sl = dict(STATE_LOSS, n_lo=5, n_hi=80)
+    phi0, pi0 = T.initial_pulse(g, 15.0, 4.0)
+    y = to_dev(W.target_noise((n, g.nth), 0.05, seed=4))
+    eng = gpu_engine(grid)
+    gpu_source(eng, grid, SRC, n)
+    out = []
+    for snaps in (0, snapshots):
+        eng.set_state(to_dev(phi0), to_dev(pi0))
+        w, ls = eng.forward_checkpointed(n, state_loss=sl, snapshots=snaps)
+        gp, gq, dA = eng.backward_checkpointed((2.0 * (w - y)).contiguous(), 1.0)
+        out.append((w, ls, gp, gq, dA))
+    (w0, ls0, gp0, gq0, dA0), (w1, ls1, gp1, gq1, dA1) = out
+    assert torch.equal(w0, w1) and ls0 == ls1
+    assert torch.equal(gp0, gp1) and torch.equal(gq0, gq1) and dA0 == dA1
+    # forced recomputation without a state loss: the residual-only sweep's gradient
+    gw = (2.0 * (w0 - y)).contiguous()
+    eng.set_state(to_dev(phi0), to_dev(pi0))
+    eng.forward_checkpointed(n, snapshots=snapshots, force_recompute=True)
+    gpf, gqf, dAf = eng.backward_checkpointed(gw)
+    eng.set_state(to_dev(phi0), to_dev(pi0))
+    eng.step(n, waveform=False)
+    eng.adjoint_begin(n, gw=gw)
+    eng.adjoint_step(n)
+    gpr, gqr, dAr = eng.adjoint_get()
+    assert torch.equal(gpf, gpr) and torch.equal(gqf, gqr) and dAf == dAr
+
+
+def test_binomial_plan_buffer_is_checked():
+    grid, n = _adjoint_case(40)
+    eng = gpu_engine(grid)
+    nb = eng.checkpoint_bytes(n, snapshots=3)
+    assert eng.checkpoint_bytes(n, snapshots=4) > nb
+    assert eng.snapshots_for_budget(n, nb) == 3
+    assert eng.snapshots_for_budget(n, 10 * nb) >= 9
+    from paper_1001_3631_amd import _lib as L
+    plan = eng._make_plan(n, 0, None, False, 3)
+    small = torch.empty(nb - 256, dtype=torch.uint8, device="cuda")
+    plan.ckpt_dev, plan.ckpt_bytes = small.data_ptr(), small.numel()
+    assert eng._lib.teuk_forward_checkpointed(eng.ctx, ctypes.byref(plan), None, None) == L.TEUK_ENOMEM
+    plan = eng._make_plan(n, 5, None, False, 3)          # interval and snapshots together
+    assert eng._lib.teuk_checkpoint_size(eng.ctx, ctypes.byref(plan), ctypes.byref(ctypes.c_size_t())) == \
+        L.TEUK_EINVAL
 
 
 def test_checkpointed_state_loss_gradient_matches_oracle():
