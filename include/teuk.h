@@ -328,7 +328,9 @@ int teuk_check_finite(teuk_ctx* ctx);
  *             blocks and the remainder as single iterations.
  *   adj_seg_rows  theta rows per wave segment of the adjoint kernel
  *             (teuk_adjoint_step_n), 4, 8 or 16; 0 in teuk_set_tuning leaves
- *             it unchanged.  Default 4 (teuk_autotune does not change it).
+ *             it unchanged.  Default 8 where 8-row segments give more
+ *             waves than the device has SIMDs, else 4 (teuk_autotune does
+ *             not change it).
  * The default (k_steps 1, seg_rows from the grid size) is set by
  * teuk_init_grid; teuk_autotune chooses (seg_rows, k_steps) by measurement.
  * EINVAL for any other values. */

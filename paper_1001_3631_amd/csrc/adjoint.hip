@@ -24,6 +24,7 @@
 
 #include <type_traits>
 
+#include "item_order.h"
 #include "kernels.h"
 #include "lw_point.h"
 #include "stream_level.h"   // wave shifts (from_next, from_prev)
@@ -74,20 +75,81 @@ __device__ __forceinline__ AngW ang_weights(const ThetaRow& R) {
 
 }  // namespace
 
+// dL/dA of one reverse iteration from the source windows alone, for the
+// launches whose waves skip their source terms (part 3): the node part
+// sum_window dt Re(conj(mu_Pi) F_n) over the full step's window and the half
+// part sum_window (dt/2) Re(conj(lambda^h_Pi) F_h) over the half step's,
+// with mu and the half-level lambda formed by the same expressions as the
+// stencil's stages 2-4 (the host uses this only for windows whose rows stay
+// in [3, nth - 4], where no pole row folds into them).  Wave b < win_t sums
+// node-window row b, wave win_t + b half-window row b, one lane per column,
+// in a fixed tree, into partial b of the iteration (part 3's other waves
+// write zeros into their partials, and the partials are summed in a fixed
+// order).
+__device__ __forceinline__ void source_dA_row(const AdjointParams& P, int b, int lane) {
+    const int4 org = *P.org;
+    const bool half = b >= P.win_t;
+    const int dr = half ? b - P.win_t : b;
+    const int dc = lane;
+    const double dt = P.dt, hdt = 0.5 * P.dt, inv_hr = P.inv_hr;
+    double v = 0.0;
+    if (dc < P.win_r) {
+        const int c = dr * P.win_r + dc;
+        if (!half) {
+            const int r = org.w + dr, i = org.z + dc;
+            if (r >= 1 && r <= P.nth - 2 && i >= 1 && i <= P.nr - 2)
+                v = dt * re_dot_conj(P.lam_pi[static_cast<size_t>(r) * P.ld + i], P.fn[c]);
+        } else {
+            const int r = org.y + dr, i = org.x + dc;
+            if (r >= 1 && r <= P.nth - 2 && i >= 0 && i <= P.nr - 2) {
+                const ThetaRow R = P.rows[r];
+                // stage 2/3 at nodes i and i + 1: Pi~ and dPi sources (zero off
+                // the interior columns), then stage 4's half-level lambda_Pi
+                double2 aq[2], dqv[2];
+                for (int t = 0; t < 2; ++t) {
+                    const int ii = i + t;
+                    double2 nq = cz(), ndq = cz();
+                    if (ii >= 1 && ii <= P.nr - 2) {
+                        const double2 p = P.lam_phi[static_cast<size_t>(r) * P.ld + ii];
+                        const double2 q = P.lam_pi[static_cast<size_t>(r) * P.ld + ii];
+                        const Coef cf = coef_at(load_rcol(P.rnode, P.nr, ii), R.cos_th, R.sin2, P.kerr != 0);
+                        const double2 ctq = cmul_conj(cf.ct, q);
+                        nq = make_double2(dt * (p.x - ctq.x), dt * (p.y - ctq.y));
+                        ndq = make_double2(dt * cf.b * q.x, dt * cf.b * q.y);
+                    }
+                    aq[t] = make_double2(0.5 * nq.x, 0.5 * nq.y);
+                    dqv[t] = make_double2(ndq.x * inv_hr, ndq.y * inv_hr);
+                }
+                const double2 hq = c_add(c_add(aq[0], dqv[0]), c_sub(aq[1], dqv[1]));
+                v = hdt * re_dot_conj(hq, P.fh[c]);
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
+    if (dc == 0) P.dA_part[b] = v;
+}
+
+// Rows a segment must keep from the poles to take the interior form:
+// jlo >= kAdjLoRows, jlo + SEG <= nth - kAdjHiRows (the stages read rows
+// jlo-4 .. jhi+5 and fold the pole rows into rows 1, 2, nth-3, nth-2).
+constexpr int kAdjLoRows = 7, kAdjHiRows = 7;
+
+// Blocks at the front of a part-3 launch that compute dL/dA from the windows
+// (four window rows per block).
+__host__ __device__ __forceinline__ int dA_blocks(int win_t) { return (2 * win_t + 3) / 4; }
+
 // PART selects the waves a launch runs: 0 all of them; 1 those that meet no
 // source window; 2 those that do (its grid covers only the rectangle of
 // items near the windows, P.sub_*); 3 all of them without their source
-// terms (dL/dA then comes from adjoint_source_dA_kernel).  A launch of part 1
-// or 3 carries no source bodies and so fits 248 VGPRs at seg 4 (two waves
-// per SIMD, no spills), where the kernel with all four bodies takes 264 (one
-// wave per SIMD).  Parts 1 and 2 together run every wave once, each through
+// terms, dL/dA coming from the window rows that the launch's first blocks
+// sum (source_dA_row).  A launch of part 1 or 3 carries no source bodies and
+// so fits two waves per SIMD without spills at seg 4 (248 VGPRs) and 16;
+// at seg 8 a few registers of the general form spill.  The kernel with all
+// four bodies runs one wave per SIMD.  Parts 1 and 2 together run every wave once, each through
 // the same body as part 0; the source terms only add to dL/dA, so every
 // part gives lambda^n the same bits.
 template <int SEG, int PART>
-__global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
-    // rows jlo-4 .. jhi+5 (jhi - jlo <= SEG + 2).  Output row r needs mu rows
-    // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
-    constexpr int NT = SEG + 12;
+__device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const ThetaRow* __restrict__ rows) {
     const int lane = threadIdx.x & 63;
     // wave-uniform work item in a scalar register (row branches become scalar
     // and the angular records, a separate __restrict__ argument, are fetched
@@ -99,9 +161,34 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
         const int a = local / P.sub_ng;
         item = (P.sub_s0 + a) * P.nseg + P.sub_g0 + (local - a * P.sub_ng);
     } else {
-        const int wg = a_xcd_remap(blockIdx.x, gridDim.x);
-        item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
-        if (item >= P.nstrips * P.nseg) return;
+        // part 3: the window dL/dA blocks first; then the frame waves (round
+        // robin over the XCDs), then the interior ones (each XCD a contiguous
+        // range)
+        int blk = blockIdx.x, nblk = gridDim.x;
+        if constexpr (PART == 3) {
+            const int nd = dA_blocks(P.win_t);
+            if (blk < nd) {
+                const int b = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+                if (b < 2 * P.win_t) source_dA_row(P, b, lane);
+                return;
+            }
+            blk -= nd;
+            nblk -= nd;
+        }
+        const ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kAdjLoRows, kAdjHiRows);
+        const int fb = (o.frame + 3) / 4;
+        if (blk < fb) {
+            const int f = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+            if (f >= o.frame) return;
+            item = frame_item(o, P.nseg, f);
+        } else {
+            const int wg = a_xcd_remap(blk - fb, nblk - fb);
+            const int k = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+            if (k >= o.interior) return;
+            item = interior_item(o, P.nseg, k);
+        }
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item < 0 || item >= P.nstrips * P.nseg) return;
     }
     const int strip = item / P.nseg;
     const int seg = item - strip * P.nseg;
@@ -133,10 +220,24 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
     // SRC: a source window meets the wave's output rows and columns; without
     // it the wave's source terms are all zero and are skipped.  (A lookup is a
     // load used at once, and its wait also waits for every load before it.)
-    auto body = [&](auto interior_tag, auto src_tag) {
+    // The body over output rows [jlo, jhi) at segment length S (the last
+    // segment of a column of segments may hold up to S + 2 rows).
+    auto body = [&](auto interior_tag, auto src_tag, auto seg_tag, const int jlo, const int jhi) {
     constexpr bool FAST = decltype(interior_tag)::value;
     constexpr bool SRC = decltype(src_tag)::value;
-    const int jhi_ = FAST ? jlo + SEG : jhi;
+    constexpr int S = decltype(seg_tag)::value;
+    // rows jlo-4 .. jhi+5 (jhi - jlo <= S + 2).  Output row r needs mu rows
+    // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
+    constexpr int NT = S + 12;
+    const int jhi_ = FAST ? jlo + S : jhi;
+    // Row lags of the stages behind the row being loaded: node sources 2,
+    // half-level lambda 3, half sources L5, output L7.  A half-level pole
+    // fold reaches two rows ahead, so the general form runs the half sources
+    // at 5 and the output at 6; the interior form has no folds and runs them
+    // at 3 and 4, which keeps two fewer rows of mu and of the half-level
+    // lambda live.
+    constexpr int L5 = FAST ? 3 : 5;
+    constexpr int L7 = FAST ? 4 : 6;
     double2 lP[NT], lQ[NT];          // lambda^{n+1}, own column, row jlo-4+t
     double2 mP[NT], mQ[NT];          // mu (after the boundary transpose)
     double2 nQ[NT], nD[NT], nDQ[NT], nC[NT], nW[NT];   // node-level sources
@@ -145,10 +246,10 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
 
     // Angular records of rows jlo-4+u: every stage at iteration it reads
     // rows at fixed offsets from its k, the newest being u = it - 2 (stage
-    // 2/3).  For SEG <= 4 each is read once, one iteration before that first
+    // 2/3).  For S <= 4 each is read once, one iteration before that first
     // use, into scalar registers (for longer segments the window's scalar
     // registers spill and each record is read where it is used).
-    constexpr bool WINDOW = SEG <= 4;
+    constexpr bool WINDOW = S <= 4;
     ThetaRow Rw[NT];
     auto fetch_rec = [&](int u) {
         const int row = jlo - 4 + u;
@@ -159,7 +260,7 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
         const int jj = jlo - 4 + it;
-        if (FAST ? it > SEG + 9 : jj > jhi + 5) continue;
+        if (FAST ? it > S + 3 + L7 : jj > jhi + L7 - 1) continue;
         if (WINDOW && it >= 1) fetch_rec(it - 1);
         // ---- 1. load lambda^{n+1}(i, jj) ----
         {
@@ -234,11 +335,11 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 hP[k] = hQ[k] = cz();
             }
         }
-        // ---- 5./6. folded half-level lambda and half sources at r2 = jj - 5 ----
-        // (the first half row any output needs is jlo - 1, reached at it = 8)
-        if (it >= 8) {
-            const int r2 = jj - 5;
-            const int k = it - 5;
+        // ---- 5./6. folded half-level lambda and half sources at r2 = jj - L5 ----
+        // (the first half row any output needs is jlo - 1, reached at it = 3 + L5)
+        if (it >= 3 + L5) {
+            const int r2 = jj - L5;
+            const int k = it - L5;
             yW[k] = cC[k] = qb[k] = dp[k] = dq[k] = cz();
             if (FAST || (r2 >= 1 && r2 <= nth - 2 && has_half)) {
                 double2 p = hP[k], q = hQ[k];
@@ -265,10 +366,10 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 }
             }
         }
-        // ---- 7./8. lambda^n at (i, r3), r3 = jj - 6 ----
-        if (it >= 8) {
-            const int r3 = jj - 6;
-            const int k = it - 6;
+        // ---- 7./8. lambda^n at (i, r3), r3 = jj - L7 ----
+        if (it >= 2 + L7) {
+            const int r3 = jj - L7;
+            const int k = it - L7;
             double2 pb = cz();
             if (FAST || (r3 >= 0 && r3 < nth)) {
                 pb = cC[k];
@@ -307,95 +408,61 @@ __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const 
                 P.out_pi[static_cast<size_t>(r3) * ld + i] = oQ;
             }
         }
+        // at 8 rows and more, keep the scheduler from hoisting work across
+        // rows: the live window then fits two waves per SIMD
+        if constexpr (S >= 8) __builtin_amdgcn_sched_barrier(0);
     }
     };
 
     const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
-                          jlo >= 7 && jlo + SEG <= nth - 7;
+                          jlo >= kAdjLoRows && jlo + SEG <= nth - kAdjHiRows;
     // (the launcher sets both window tables or neither)
     const int i0 = strip * 62 - 1;
     // (part 3 treats every wave as one without source terms)
     const bool src = PART != 3 && P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
                      (window_meets(org, false, P.win_r, P.win_t, i0, jlo, jhi - 1) ||
                       window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
+    using SegT = std::integral_constant<int, SEG>;
     if (src) {   // uniform per wave
         if constexpr (PART == 1 || PART == 3) {
             return;
         } else {
             if (interior)
-                body(std::true_type{}, std::true_type{});
+                body(std::true_type{}, std::true_type{}, SegT{}, jlo, jhi);
             else
-                body(std::false_type{}, std::true_type{});
+                body(std::false_type{}, std::true_type{}, SegT{}, jlo, jhi);
         }
     } else {
         if constexpr (PART == 2) {
             return;
         } else {
             if (interior)
-                body(std::true_type{}, std::false_type{});
+                body(std::true_type{}, std::false_type{}, SegT{}, jlo, jhi);
             else
-                body(std::false_type{}, std::false_type{});
+                body(std::false_type{}, std::false_type{}, SegT{}, jlo, jhi);
         }
     }
     // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
-    if (P.dA_part != nullptr) {
+    // (in part 3 the window blocks own partials 0 .. 2 win_t - 1)
+    if (P.dA_part != nullptr && (PART != 3 || item >= 2 * P.win_t)) {
         double v = dA;
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
         if (lane == 0) P.dA_part[item] = v;
     }
 }
 
-// dL/dA of one reverse iteration from the source windows alone, for the
-// launches whose waves skip their source terms (part 3): the node part
-// sum_window dt Re(conj(mu_Pi) F_n) over the full step's window and the half
-// part sum_window (dt/2) Re(conj(lambda^h_Pi) F_h) over the half step's,
-// with mu and the half-level lambda formed by the same expressions as the
-// stencil's stages 2-4 (the host uses this only for windows whose rows stay
-// in [3, nth - 4], where no pole row folds into them).  Block b < win_t sums
-// node-window row b, block win_t + b half-window row b, one lane per column,
-// in a fixed tree; its sum replaces partial b of the iteration (part 3 wrote
-// zeros for every wave, and the partials are summed in a fixed order).
-__global__ void __launch_bounds__(64) adjoint_source_dA_kernel(AdjointParams P) {
-    const int4 org = *P.org;
-    const bool half = static_cast<int>(blockIdx.x) >= P.win_t;
-    const int dr = half ? blockIdx.x - P.win_t : blockIdx.x;
-    const int dc = threadIdx.x;
-    const double dt = P.dt, hdt = 0.5 * P.dt, inv_hr = P.inv_hr;
-    double v = 0.0;
-    if (dc < P.win_r) {
-        const int c = dr * P.win_r + dc;
-        if (!half) {
-            const int r = org.w + dr, i = org.z + dc;
-            if (r >= 1 && r <= P.nth - 2 && i >= 1 && i <= P.nr - 2)
-                v = dt * re_dot_conj(P.lam_pi[static_cast<size_t>(r) * P.ld + i], P.fn[c]);
-        } else {
-            const int r = org.y + dr, i = org.x + dc;
-            if (r >= 1 && r <= P.nth - 2 && i >= 0 && i <= P.nr - 2) {
-                const ThetaRow R = P.rows[r];
-                // stage 2/3 at nodes i and i + 1: Pi~ and dPi sources (zero off
-                // the interior columns), then stage 4's half-level lambda_Pi
-                double2 aq[2], dqv[2];
-                for (int t = 0; t < 2; ++t) {
-                    const int ii = i + t;
-                    double2 nq = cz(), ndq = cz();
-                    if (ii >= 1 && ii <= P.nr - 2) {
-                        const double2 p = P.lam_phi[static_cast<size_t>(r) * P.ld + ii];
-                        const double2 q = P.lam_pi[static_cast<size_t>(r) * P.ld + ii];
-                        const Coef cf = coef_at(load_rcol(P.rnode, P.nr, ii), R.cos_th, R.sin2, P.kerr != 0);
-                        const double2 ctq = cmul_conj(cf.ct, q);
-                        nq = make_double2(dt * (p.x - ctq.x), dt * (p.y - ctq.y));
-                        ndq = make_double2(dt * cf.b * q.x, dt * cf.b * q.y);
-                    }
-                    aq[t] = make_double2(0.5 * nq.x, 0.5 * nq.y);
-                    dqv[t] = make_double2(ndq.x * inv_hr, ndq.y * inv_hr);
-                }
-                const double2 hq = c_add(c_add(aq[0], dqv[0]), c_sub(aq[1], dqv[1]));
-                v = hdt * re_dot_conj(hq, P.fh[c]);
-            }
-        }
-    }
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off);
-    if (dc == 0) P.dA_part[blockIdx.x] = v;
+template <int SEG, int PART>
+__global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
+    adjoint_iteration<SEG, PART>(P, rows);
+}
+
+// The same iteration held to two waves per SIMD, for the launches without
+// source bodies at segments of 8 and 16 rows (a few registers of the
+// general form may spill; the interior form fits).
+template <int SEG, int PART>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lw_adjoint2_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
+    adjoint_iteration<SEG, PART>(P, rows);
 }
 
 // Sum n per-wave partials into *acc in a fixed order (the result depends only
@@ -454,12 +521,13 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
 }
 
 bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
-    return seg == 4 && nstrips * nseg > nsimd && nstrips <= INT16_MAX && nseg <= INT16_MAX;
+    return nstrips * nseg > nsimd && nstrips <= INT16_MAX && nseg <= INT16_MAX;
 }
 
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream, bool source_by_window) {
     const int items = P.nstrips * P.nseg;
-    const dim3 grid((items + 3) / 4), block(256);
+    const dim3 grid(ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kAdjLoRows, kAdjHiRows))),
+        block(256);
     // With a source on a grid of more waves than SIMDs, the waves without
     // it run in a launch of their own at two waves per SIMD (seg 4), and the
     // few with it in a second launch.  Smaller grids run one wave per SIMD
@@ -469,9 +537,8 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
         case 4:
             if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
                 // every wave without its source terms at two waves per SIMD,
-                // then dL/dA from the windows in one block
-                hipLaunchKernelGGL((lw_adjoint_kernel<4, 3>), grid, block, 0, stream, P, P.rows);
-                hipLaunchKernelGGL(adjoint_source_dA_kernel, dim3(2 * P.win_t), dim3(64), 0, stream, P);
+                // and dL/dA from the windows in the launch's first blocks
+                hipLaunchKernelGGL((lw_adjoint_kernel<4, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
             } else if (split) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
                 const int sub = P.sub_ns * P.sub_ng;
@@ -484,8 +551,36 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
             }
             break;
-        case 8: hipLaunchKernelGGL((lw_adjoint_kernel<8, 0>), grid, block, 0, stream, P, P.rows); break;
-        case 16: hipLaunchKernelGGL((lw_adjoint_kernel<16, 0>), grid, block, 0, stream, P, P.rows); break;
+        case 8:
+            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
+            } else if (split) {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
+                const int sub = P.sub_ns * P.sub_ng;
+                if (sub > 0)
+                    hipLaunchKernelGGL((lw_adjoint_kernel<8, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
+                                       P.rows);
+            } else if (P.fh != nullptr && P.fn != nullptr) {
+                hipLaunchKernelGGL((lw_adjoint_kernel<8, 0>), grid, block, 0, stream, P, P.rows);
+            } else {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
+            }
+            break;
+        case 16:
+            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<16, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
+            } else if (split) {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<16, 1>), grid, block, 0, stream, P, P.rows);
+                const int sub = P.sub_ns * P.sub_ng;
+                if (sub > 0)
+                    hipLaunchKernelGGL((lw_adjoint_kernel<16, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
+                                       P.rows);
+            } else if (P.fh != nullptr && P.fn != nullptr) {
+                hipLaunchKernelGGL((lw_adjoint_kernel<16, 0>), grid, block, 0, stream, P, P.rows);
+            } else {
+                hipLaunchKernelGGL((lw_adjoint2_kernel<16, 1>), grid, block, 0, stream, P, P.rows);
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

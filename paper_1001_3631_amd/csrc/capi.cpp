@@ -314,9 +314,11 @@ int teuk_detail::make_ctx(const teuk_grid_desc* d, const teuk_ws_request* req, v
     }
     // default segment: 8 rows when that still gives at least one wave per
     // SIMD, else 4; the autotuner refines this by measurement.  The adjoint
-    // runs 4-row segments (fastest on every grid measured, large or small).
+    // runs 8-row segments where they give more waves than SIMDs (its
+    // launches then run two waves per SIMD without source bodies), else 4
+    // (each wave alone on its SIMD: shorter segments finish sooner).
     set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= c->nsimd) ? 8 : 4, 1);
-    set_adjoint_segment(c, 4);
+    set_adjoint_segment(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) > c->nsimd) ? 8 : 4);
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
     const WsLayout& L = c->lay;
     for (int l = 0; l < 2; ++l)
@@ -775,6 +777,8 @@ static int check_plan(const teuk_ctx* c, const teuk_grad_plan* p, int64_t* inter
     return TEUK_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Byte offsets inside a plan's checkpoint buffer: 2K snapshot planes (K =
@@ -828,6 +832,8 @@ int bind_ckpt(teuk_ctx* c, const teuk_grad_plan* p, int64_t iv) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int teuk_checkpoint_schedule(int64_t nsteps, int64_t snapshots, int32_t phase, int64_t* actions, int64_t cap,
                              int64_t* count, int64_t* stats) {

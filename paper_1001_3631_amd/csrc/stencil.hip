@@ -14,6 +14,7 @@
 
 #include <type_traits>
 
+#include "item_order.h"
 #include "kernels.h"
 #include "lw_point.h"
 #include "stream_level.h"
@@ -29,16 +30,37 @@ namespace teuk {
 // written out in the kernel itself: the compiler schedules it about 8 %
 // faster than the same code reached through the inlined template (same
 // instructions on every point, so the results are bitwise identical).
+// Rows a segment must keep from the poles to take the interior form:
+// jlo >= kStepLoRows, jlo + SEG <= nth - kStepHiRows.
+constexpr int kStepLoRows = 4, kStepHiRows = 2;
+
 template <int SEG>
 __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaRow* __restrict__ rows) {
     const int lane = threadIdx.x & 63;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
     // the wave's work item, in a scalar register: everything derived from it
     // (segment rows, row branches, angular-record addresses) is then known to
     // be wave-uniform, so the row branches are scalar and the records are
-    // fetched through the scalar cache
-    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
-    if (item >= P.nstrips * P.nseg) return;   // uniform per wave
+    // fetched through the scalar cache.  The frame waves (general form) are
+    // dispatched first, round robin over the XCDs; the interior ones follow,
+    // each XCD walking a contiguous range.
+    int item;
+    {
+        const ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kStepLoRows, kStepHiRows);
+        const int fb = (o.frame + 3) / 4;
+        const int blk = blockIdx.x;
+        if (blk < fb) {
+            const int f = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+            if (f >= o.frame) return;
+            item = frame_item(o, P.nseg, f);
+        } else {
+            const int wg = xcd_remap(blk - fb, gridDim.x - fb);
+            const int k = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+            if (k >= o.interior) return;
+            item = interior_item(o, P.nseg, k);
+        }
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item < 0 || item >= P.nstrips * P.nseg) return;   // uniform per wave
+    }
     const int strip = item / P.nseg;
     const int seg = item - strip * P.nseg;
     const int i = strip * 62 - 1 + lane;
@@ -241,7 +263,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
     };
 
     const bool interior = strip >= 1 && strip * 62 + 64 <= P.nr && seg != P.nseg - 1 &&
-                          jlo >= 4 && jlo + SEG <= nth - 2;
+                          jlo >= kStepLoRows && jlo + SEG <= nth - kStepHiRows;
     const int i0 = strip * 62 - 1;
     // (the launcher sets both window tables or neither)
     const bool src = P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
@@ -383,8 +405,8 @@ bool valid_segment_rows(int seg) {
 // With events, the launch itself records them at the kernel's start and end.
 hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start,
                        hipEvent_t ev_stop) {
-    const int items = P.nstrips * P.nseg;
-    const dim3 grid((items + 3) / 4), block(256);
+    const dim3 grid(ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kStepLoRows, kStepHiRows))),
+        block(256);
     switch (seg) {
         // the angular records are a separate __restrict__ argument: read-only,
         // never aliasing the planes, so their wave-uniform loads are scalar

@@ -456,9 +456,14 @@ def test_adjoint_fullsize_gradient_vs_central_differences_32_directions():
 
 
 def test_adjoint_segment_setting():
-    """teuk_tuning.adj_seg_rows: default 4, 0 keeps the current value, the
-    stepper's own settings do not touch it, invalid values are refused."""
+    """teuk_tuning.adj_seg_rows: default 4 on a small grid and 8 where
+    8-row segments give more waves than SIMDs, 0 keeps the current value,
+    the stepper's own settings do not touch it, invalid values are refused."""
     from paper_1001_3631_amd import _lib as L
+    big = gpu_engine(W.KERR_EMRI["grid"])            # 104 strips x 16 segments of 8 rows
+    assert big.tuning["adj_seg_rows"] == (8 if 104 * 16 > 4 * torch.cuda.get_device_properties(0).multi_processor_count
+                                          else 4)
+    big.close()
     eng = gpu_engine(STEP_GRIDS[0])
     assert eng.tuning["adj_seg_rows"] == 4
     eng.set_tuning(8, 1, 16)
@@ -471,10 +476,11 @@ def test_adjoint_segment_setting():
     eng.close()
 
 
+@pytest.mark.parametrize("adj_seg", [4, 8])
 @pytest.mark.parametrize("th_cells", [None, 2.5, 124.5], ids=["equator", "near_theta0", "near_theta_pi"])
-def test_split_reverse_iteration_against_oracle(th_cells):
+def test_split_reverse_iteration_against_oracle(th_cells, adj_seg):
     """On a grid of more adjoint waves than SIMDs (6400 x 128: 3328 waves at
-    segments of 4) the reverse iteration with a source is split: with the
+    segments of 4, 1664 at 8) the reverse iteration with a source is split: with the
     windows away from the poles every wave runs without source terms and
     dL/dA comes from the windows alone; with a window that reaches the pole
     rows the waves near it run in a launch of their own.  Both against one
@@ -489,6 +495,7 @@ def test_split_reverse_iteration_against_oracle(th_cells):
     rs_p = 12.7834
     orbit = {"rs": np.full(t.shape, rs_p), "th": np.full(t.shape, th_p), "phi": 0.0307 * t}
     eng = gpu_engine(grid)
+    eng.set_tuning(8, 1, adj_seg)
     eng.set_source(np.stack([orbit["rs"], orbit["th"], orbit["phi"]], axis=1), 1.0, 2.0, 2.0, 8.0)
     src = T.Source(g, orbit, 1.0, 2.0, 2.0, 8.0)
     lp, lq = W.random_state(g.nth, g.nr, seed=61)
@@ -498,5 +505,35 @@ def test_split_reverse_iteration_against_oracle(th_cells):
     p1, q1, dA = eng.adjoint_get()
     rp, rq, rdA = T.adjoint_step(g, lp, lq, m0 - 1, src)
     e = (rel(host(p1), rp), rel(host(q1), rq), abs(dA - rdA) / abs(rdA))
-    print("split reverse iteration", th_cells, e)
+    print("split reverse iteration", th_cells, adj_seg, e)
     assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
+
+
+@pytest.mark.parametrize("th_cells", [None, 2.5], ids=["equator", "near_theta0"])
+def test_large_grid_reverse_sweep_bitwise_across_segments(th_cells):
+    """6400 x 128 with a source: the reverse sweep at adjoint segments of 4,
+    8 and 16 rows (split launches with window dL/dA, split launches with
+    a launch for the waves near a pole window, one launch) gives the same
+    lambda bit for bit; dL/dA, summed from differently grouped partials,
+    agrees to rounding."""
+    grid = W.KERR_EMRI["grid"]
+    g = T.Grid(**grid)
+    n = 6
+    th_p = 0.5 * np.pi if th_cells is None else th_cells * g.hth
+    t = np.arange(2 * n + 3) * 0.5 * g.dt
+    orbit = np.stack([np.full(t.shape, 12.7834), np.full(t.shape, th_p), 0.0307 * t], axis=1)
+    lp, lq = W.random_state(g.nth, g.nr, seed=71)
+    gw = to_dev(W.target_noise((n, g.nth), 1.0, seed=72))
+    outs = []
+    for seg in (4, 8, 16):
+        eng = gpu_engine(grid)
+        eng.set_tuning(8, 1, seg)
+        eng.set_source(orbit, 1.0, 2.0, 2.0, 8.0)
+        eng.adjoint_begin(n, to_dev(lp), to_dev(lq), gw=gw)
+        eng.adjoint_step(n)
+        p, q, dA = eng.adjoint_get()
+        outs.append((p, q, dA))
+        eng.close()
+    for p, q, dA in outs[1:]:
+        assert torch.equal(p, outs[0][0]) and torch.equal(q, outs[0][1])
+        assert abs(dA - outs[0][2]) <= 1e-13 * abs(outs[0][2]), (dA, outs[0][2])

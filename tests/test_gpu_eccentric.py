@@ -120,9 +120,9 @@ def test_adjoint_at_scale_instance_full_size():
     eng.close()
 
 
-@pytest.mark.parametrize("adj_seg", [4, 8])
+@pytest.mark.parametrize("adj_seg", [4, 8, 16])
 def test_adjoint_at_scale_one_reverse_iteration_against_oracle(adj_seg):
-    """One GPU reverse iteration on 12800 x 256 (13248 or 6624 waves) with
+    """One GPU reverse iteration on 12800 x 256 (13248, 6624 or 3312 waves) with
     the eccentric source, from a lambda made by 20 GPU reverse iterations
     from a seeded state, against one oracle reverse iteration on the same
     lambda: every point, including the strip seams inside the source window."""
