@@ -21,9 +21,13 @@ element:
     workload after its first iterations), the whole rectangle around the
     particle.
 
+Each workload has a second fixture, <case>_amp, with the oracle's own
+sensitivity: its samples after an early iteration n1, and the final samples
+of a run whose state at n1 was moved by a relative 1e-12 (job_amp).
+
 Usage:  python tests/golden/make_golden.py CASE [CASE ...]
 Cases:  kerr_emri_6400x128, adjoint_3200x64_forward, batched_smallest4,
-        adjoint_at_scale_first1000
+        adjoint_at_scale_first1000, and each of them with the suffix _amp
 Writes tests/golden/<case>.npz (one file per case).
 """
 
@@ -94,29 +98,30 @@ def source_cols(g, rs_p):
 
 
 # ---------------------------------------------------------------------------
-# One oracle run per job; each returns (key, dict of arrays, metadata)
+# Workloads: each setup returns the oracle grid, initial state, source, the
+# iteration count and the sampling (identical for every fixture of a case)
 # ---------------------------------------------------------------------------
 
-def job_kerr_emri():
+def setup_kerr_emri():
     cfg = W.KERR_EMRI
     g = T.Grid(**cfg["grid"])
     n = cfg["steps"]
     src = circular_source(g, cfg["source"], n)
     z = np.zeros((g.nth, g.nr), np.complex128)
-    phi, pi, w = T.evolve(g, z, z, n, src)
-    d = pack(phi, pi, w, g, stride=100, extra_cols=source_cols(g, src.orbit["rs"][0]), seed=2)
-    return "", d, dict(workload=cfg["name"], steps=n, grid=cfg["grid"], source=cfg["source"], init="zero")
+    kw = dict(stride=100, extra_cols=source_cols(g, src.orbit["rs"][0]), seed=2)
+    return g, z, z, src, n, kw, dict(workload=cfg["name"], steps=n, grid=cfg["grid"], source=cfg["source"],
+                                     init="zero")
 
 
-def job_adjoint_forward():
+def setup_adjoint_forward():
     cfg = W.ADJOINT
     g = T.Grid(**cfg["grid"])
     n = cfg["steps"]
     src = circular_source(g, cfg["source"], n)
     phi0, pi0 = T.initial_pulse(g, **cfg["pulse"])
-    phi, pi, w = T.evolve(g, phi0, pi0, n, src)
-    d = pack(phi, pi, w, g, stride=50, extra_cols=source_cols(g, src.orbit["rs"][0]), seed=4)
-    return "", d, dict(workload=cfg["name"], steps=n, grid=cfg["grid"], source=cfg["source"], pulse=cfg["pulse"])
+    kw = dict(stride=50, extra_cols=source_cols(g, src.orbit["rs"][0]), seed=4)
+    return g, phi0, pi0, src, n, kw, dict(workload=cfg["name"], steps=n, grid=cfg["grid"], source=cfg["source"],
+                                          pulse=cfg["pulse"])
 
 
 BATCH_STEPS = 10000
@@ -133,20 +138,20 @@ def batched_smallest4():
     return [pick[m] for m in sorted(pick)]
 
 
-def job_batched(k):
+def setup_batched(k):
     d0 = W.batched_instances()[k]
     g = T.Grid(**d0["grid"])
     phi0, pi0 = T.initial_pulse(g, **d0["pulse"])
-    phi, pi, w = T.evolve(g, phi0, pi0, BATCH_STEPS)
-    d = pack(phi, pi, w, g, stride=50, npts=4096, seed=30 + k)
-    return f"i{k}_", d, dict(instance=k, grid=d0["grid"], pulse=d0["pulse"], steps=BATCH_STEPS)
+    kw = dict(stride=50, npts=4096, seed=30 + k)
+    return g, phi0, pi0, None, BATCH_STEPS, kw, dict(instance=k, grid=d0["grid"], pulse=d0["pulse"],
+                                                     steps=BATCH_STEPS)
 
 
 SCALE_STEPS = 1000
 SCALE_PICK = (0, 7, 9, 13)   # spans a (0.04 .. 0.95), m (2, 3), e (0.12 .. 0.48), the closest orbit (p = 8.0)
 
 
-def job_scale(k):
+def setup_scale(k):
     cfg = W.ADJOINT_AT_SCALE
     d0 = W.adjoint_at_scale_instances()[k]
     g = T.Grid(**d0["grid"])
@@ -155,19 +160,67 @@ def job_scale(k):
     s = cfg["source"]
     src = T.Source(g, orbit, s["amplitude"], s["sigma_r_cells"], s["sigma_th_cells"], s["cutoff_sigmas"])
     z = np.zeros((g.nth, g.nr), np.complex128)
-    phi, pi, w = T.evolve(g, z, z, SCALE_STEPS, src)
     i_p = int(np.rint((orbit["rs"][-1] - g.rs_min) / g.hr))
     j_p = g.nth // 2
     rect = (j_p - 32, j_p + 33, i_p - 100, i_p + 101)
-    d = pack(phi, pi, w, g, stride=10, extra_cols=(i_p,), npts=4096, seed=50 + k, rect=rect, full_rows=False)
-    return f"i{k}_", d, dict(instance=k, grid=d0["grid"], orbit=o, source=s, steps=SCALE_STEPS, init="zero")
+    kw = dict(stride=10, extra_cols=(i_p,), npts=4096, seed=50 + k, rect=rect, full_rows=False)
+    return g, z, z, src, SCALE_STEPS, kw, dict(instance=k, grid=d0["grid"], orbit=o, source=s,
+                                               steps=SCALE_STEPS, init="zero")
+
+
+# ---------------------------------------------------------------------------
+# Jobs
+# ---------------------------------------------------------------------------
+
+def job_main(setup, args, prefix):
+    """The full run: samples of the final state and waveform."""
+    g, p0, q0, src, n, kw, meta = setup(*args)
+    phi, pi, w = T.evolve(g, p0, q0, n, src)
+    return prefix, pack(phi, pi, w, g, **kw), meta
+
+
+AMP_REL = 1e-12
+
+
+def job_amp(setup, args, prefix, n1):
+    """The oracle's own sensitivity.  Samples of the state after n1
+    iterations (an early point where the GPU must still agree to 1e-12),
+    and samples of the final state of a second run whose state at n1 was
+    moved by a seeded random relative perturbation of 1e-12 (Phi and Pi each)
+    and then evolved to the end.  The difference between these samples and
+    the main fixture's is what a 1e-12 difference at n1 grows into by the
+    end: the discrete problem's own amplification."""
+    g, p0, q0, src, n, kw, meta = setup(*args)
+    p, q, w1 = T.evolve(g, p0, q0, n1, src)
+    mid = pack(p, q, w1, g, **dict(kw, stride=min(kw["stride"], n1)))
+    rng = np.random.default_rng(12345)
+
+    def perturb(x):
+        d = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
+        return x + AMP_REL * np.linalg.norm(x) / np.linalg.norm(d) * d
+
+    p, q = perturb(p), perturb(q)
+    w = [w1]
+    for k in range(n1, n):
+        p, q = T.step(g, p, q, k, src)
+        w.append(p[:, g.i_ext].copy()[None, :])   # a copy: a view would keep every state alive
+    end = pack(p, q, np.concatenate(w), g, **kw)
+    d = {"mid_" + k: v for k, v in mid.items()}
+    d.update({"pert_" + k: v for k, v in end.items()})
+    d["n1"] = np.int64(n1)
+    d["amp_rel"] = np.float64(AMP_REL)
+    return prefix, d, dict(meta, n1=n1)
 
 
 CASES = {
-    "kerr_emri_6400x128": lambda: [(job_kerr_emri, ())],
-    "adjoint_3200x64_forward": lambda: [(job_adjoint_forward, ())],
-    "batched_smallest4": lambda: [(job_batched, (k,)) for k in batched_smallest4()],
-    "adjoint_at_scale_first1000": lambda: [(job_scale, (k,)) for k in SCALE_PICK],
+    "kerr_emri_6400x128": lambda: [(job_main, (setup_kerr_emri, (), ""))],
+    "adjoint_3200x64_forward": lambda: [(job_main, (setup_adjoint_forward, (), ""))],
+    "batched_smallest4": lambda: [(job_main, (setup_batched, (k,), f"i{k}_")) for k in batched_smallest4()],
+    "adjoint_at_scale_first1000": lambda: [(job_main, (setup_scale, (k,), f"i{k}_")) for k in SCALE_PICK],
+    "kerr_emri_6400x128_amp": lambda: [(job_amp, (setup_kerr_emri, (), "", 2000))],
+    "adjoint_3200x64_forward_amp": lambda: [(job_amp, (setup_adjoint_forward, (), "", 2000))],
+    "batched_smallest4_amp": lambda: [(job_amp, (setup_batched, (k,), f"i{k}_", 1000)) for k in batched_smallest4()],
+    "adjoint_at_scale_first1000_amp": lambda: [(job_amp, (setup_scale, (k,), f"i{k}_", 250)) for k in SCALE_PICK],
 }
 
 
