@@ -175,7 +175,11 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
             blk -= nd;
             nblk -= nd;
         }
-        const ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kAdjLoRows, kAdjHiRows);
+        ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kAdjLoRows, kAdjHiRows);
+        if (!P.frame_first) {   // plain item order, each XCD a contiguous range
+            o.frame = 0;
+            o.interior = P.nstrips * P.nseg;
+        }
         const int fb = (o.frame + 3) / 4;
         if (blk < fb) {
             const int f = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
@@ -185,7 +189,7 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
             const int wg = a_xcd_remap(blk - fb, nblk - fb);
             const int k = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
             if (k >= o.interior) return;
-            item = interior_item(o, P.nseg, k);
+            item = P.frame_first ? interior_item(o, P.nseg, k) : k;
         }
         item = __builtin_amdgcn_readfirstlane(item);
         if (item < 0 || item >= P.nstrips * P.nseg) return;
@@ -526,7 +530,9 @@ bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
 
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream, bool source_by_window) {
     const int items = P.nstrips * P.nseg;
-    const dim3 grid(ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kAdjLoRows, kAdjHiRows))),
+    const dim3 grid(P.frame_first ? ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kAdjLoRows,
+                                                              kAdjHiRows))
+                                  : (items + 3) / 4),
         block(256);
     // With a source on a grid of more waves than SIMDs, the waves without
     // it run in a launch of their own at two waves per SIMD (seg 4), and the

@@ -15,6 +15,7 @@
 #include "../../include/teuk.h"
 #include "ctx.h"
 #include "geometry.h"
+#include "item_order.h"
 #include "kernels.h"
 #include "revolve.h"
 
@@ -567,6 +568,7 @@ int teuk_step_n(teuk_ctx* c, int64_t nsteps, void* waveform) {
     P.i_ext = G.i_ext;
     P.win_r = c->win_r;
     P.win_t = c->win_t;
+    P.frame_first = teuk::use_frame_first(c->nstrips * c->nseg, c->nsimd) ? 1 : 0;
     double2* wave = static_cast<double2*>(waveform);
     int64_t k = 0;
     while (k < nsteps) {
@@ -685,6 +687,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
     P.win_t = c->win_t;
     P.sub_s0 = P.sub_ns = P.sub_g0 = P.sub_ng = 0;
     const int items = c->nstrips * c->adj_nseg;
+    P.frame_first = teuk::use_frame_first(items, c->nsimd) ? 1 : 0;
     if (c->part_items != items) {
         if (int rc = flush_partials(c)) return rc;
         c->part_items = items;

@@ -57,4 +57,9 @@ __host__ __device__ inline int interior_item(const ItemOrder& o, int nseg, int k
 // Workgroups (4 waves each) of a launch in this order.
 __host__ __device__ inline int ordered_blocks(const ItemOrder& o) { return (o.frame + 3) / 4 + (o.interior + 3) / 4; }
 
+// The order pays only when a launch has more waves than the device has
+// SIMDs: with every wave resident at once, sending a strip's frame and
+// interior segments to different XCDs only costs L2 locality.
+__host__ __device__ inline bool use_frame_first(int items, int nsimd) { return items > nsimd; }
+
 }  // namespace teuk

@@ -39,6 +39,7 @@ struct StepParams {
     const double2* fn;          // nodes: [win_t][win_r]
     const int4* org;            // window origins: half (col0,row0), node (col0,row0)
     int win_r, win_t;
+    int frame_first = 0;        // dispatch the general-form waves first (item_order.h)
 };
 
 // One instance of a batched launch (homogeneous evolution; see lw_batch_kernel).
@@ -126,6 +127,7 @@ struct AdjointParams {
     // only these
     int16_t sub_s0, sub_ns, sub_g0, sub_ng;
     uint8_t even, kerr;
+    uint8_t frame_first = 0;    // dispatch the general-form waves first (item_order.h)
 };
 
 hipError_t launch_region_sumsq(const double2* phi, int ld, int i0, int i1, int j0, int j1, double* part,

@@ -45,7 +45,11 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
     // each XCD walking a contiguous range.
     int item;
     {
-        const ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kStepLoRows, kStepHiRows);
+        ItemOrder o = item_order(P.nr, P.nth, P.nstrips, P.nseg, SEG, kStepLoRows, kStepHiRows);
+        if (!P.frame_first) {   // plain item order, each XCD a contiguous range
+            o.frame = 0;
+            o.interior = P.nstrips * P.nseg;
+        }
         const int fb = (o.frame + 3) / 4;
         const int blk = blockIdx.x;
         if (blk < fb) {
@@ -56,7 +60,7 @@ __global__ void __launch_bounds__(256) lw_step_kernel(StepParams P, const ThetaR
             const int wg = xcd_remap(blk - fb, gridDim.x - fb);
             const int k = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
             if (k >= o.interior) return;
-            item = interior_item(o, P.nseg, k);
+            item = P.frame_first ? interior_item(o, P.nseg, k) : k;
         }
         item = __builtin_amdgcn_readfirstlane(item);
         if (item < 0 || item >= P.nstrips * P.nseg) return;   // uniform per wave
@@ -405,7 +409,9 @@ bool valid_segment_rows(int seg) {
 // With events, the launch itself records them at the kernel's start and end.
 hipError_t launch_step(const StepParams& P, int seg, hipStream_t stream, hipEvent_t ev_start,
                        hipEvent_t ev_stop) {
-    const dim3 grid(ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kStepLoRows, kStepHiRows))),
+    const dim3 grid(P.frame_first ? ordered_blocks(item_order(P.nr, P.nth, P.nstrips, P.nseg, seg, kStepLoRows,
+                                                              kStepHiRows))
+                                  : (P.nstrips * P.nseg + 3) / 4),
         block(256);
     switch (seg) {
         // the angular records are a separate __restrict__ argument: read-only,
