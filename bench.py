@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--batched-iterations", type=int, default=10000)
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the forward + checkpointed adjoint of the 16 instances on 12800 x 256")
+    ap.add_argument("--scale-instances", type=int, default=None,
+                    help="run only the first N instances of the 16 x 12800 x 256 workload (profiling)")
     ap.add_argument("--scale-iterations", type=int, default=None,
                     help="iterations per instance of that workload (default its full 50000)")
     ap.add_argument("--workload", default="kerr_emri_6400x128",
@@ -250,6 +252,8 @@ def adjoint_at_scale(args):
     src = cfg["source"]
     insts = W.adjoint_at_scale_instances(cfg["seed"], cfg["instances"])
     budget = HBM_BYTES / len(insts)
+    if args.scale_instances:
+        insts = insts[:args.scale_instances]
     tf = tb = 0.0
     pts = 0
     worst_dA = 0.0
@@ -298,7 +302,7 @@ def adjoint_at_scale(args):
         del gp, gq, gw, w, z
         eng.close()
     _, _, (reps, recomputed, _) = checkpoint_schedule(n, snapshots)
-    out = {"workload": cfg["name"], "instances": cfg["instances"], "iterations": n,
+    out = {"workload": cfg["name"], "instances": len(insts), "iterations": n,
            "schedule": "instances one after another (each fills the GPU); binomial checkpoints, "
                        "every recomputation of the schedule run in the backward",
            "snapshots_per_instance": snapshots, "repetitions": reps,

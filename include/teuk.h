@@ -346,15 +346,17 @@ int teuk_get_tuning(const teuk_ctx* ctx, teuk_tuning* out);
 /* Autotuner over the launch configurations above.
  * Times every valid (seg_rows, k_steps) pair on this context's grid with HIP
  * events (warm-up, then the best of three timed runs of a fixed number of
- * iterations, without source or extraction), keeps the fastest as the
- * context's tuning, and leaves the state, iteration count and source batch
- * as they were (the state is saved to and restored from host memory;
- * synchronizes the stream).
+ * iterations, without extraction, with the context's source when its orbit
+ * table covers the 624 trial iterations from the current one, else without),
+ * keeps the fastest as the context's tuning, and leaves the state,
+ * iteration count and source as they were (the state is saved to and
+ * restored from host memory; synchronizes the stream).
  *   cache_path  host string or NULL.  A text file of lines
  *               "<key>\t<seg_rows>\t<k_steps>\t<us per iteration>", where the
- *               key names the device architecture, nr, nth, whether a != 0
- *               and whether the dissipation is on, and a hash of the kernel
- *               sources the library was built from.  If a line with this
+ *               key names the device architecture, nr, nth, whether a != 0,
+ *               whether the dissipation is on, whether the trials ran with
+ *               the source, and a hash of the kernel sources the library
+ *               was built from.  If a line with this
  *               context's key exists its pair is applied without measuring;
  *               otherwise the measured choice is appended (the file is
  *               created if missing).  Unreadable/unwritable file: EINVAL.

@@ -1173,9 +1173,19 @@ int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, i
     HIP_TRY(hipGetDeviceProperties(&prop, dev), "autotune device properties");
     std::string arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
+    // Trials: kWarm untimed then kReps timed runs of kIters iterations per
+    // candidate, one after another from the current iteration.  They run
+    // with the context's source when its orbit table covers them all (the
+    // waves that meet a window take the longer general body, and how long
+    // they make a launch depends on the segment length), else without.
+    constexpr int kWarm = 8, kIters = 32, kReps = 3;   // multiples of every blocked depth
+    constexpr int kCandidates = sizeof(teuk::kSegVariants) / sizeof(teuk::kSegVariants[0]) +
+                                sizeof(teuk::kBlockVariants) / sizeof(teuk::kBlockVariants[0]);
+    const int64_t trial_iters = static_cast<int64_t>(kCandidates) * (kWarm + kReps * kIters);
+    const bool with_src = c->has_src && 2 * (c->steps_done + trial_iters) + 1 < c->nsamples;
     char keybuf[256];
-    std::snprintf(keybuf, sizeof(keybuf), "%s nr=%d nth=%d kerr=%d ko=%d src=%s", arch.c_str(), G.nr, G.nth,
-                  G.a != 0.0 ? 1 : 0, c->ko_c != 0.0 ? 1 : 0, TEUK_SOURCE_HASH);
+    std::snprintf(keybuf, sizeof(keybuf), "%s nr=%d nth=%d kerr=%d ko=%d source=%d src=%s", arch.c_str(), G.nr,
+                  G.nth, G.a != 0.0 ? 1 : 0, c->ko_c != 0.0 ? 1 : 0, with_src ? 1 : 0, TEUK_SOURCE_HASH);
     const std::string key = keybuf;
 
     auto emit = [&](const std::vector<teuk_tune_entry>& v) {
@@ -1257,9 +1267,8 @@ int teuk_autotune(teuk_ctx* c, const char* cache_path, teuk_tune_entry* table, i
         set_tuning_fields(c, seg0, k0);
         return hip_fail(e, "autotune setup");
     }
-    c->has_src = false;
+    c->has_src = with_src;
     c->timing = false;
-    constexpr int kWarm = 8, kIters = 32, kReps = 3;   // multiples of every blocked depth
     for (auto& t : cand) {
         set_tuning_fields(c, t.seg_rows, t.k_steps);
         int rc = teuk_step_n(c, kWarm, nullptr);

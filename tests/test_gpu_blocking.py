@@ -119,6 +119,32 @@ def test_invalid_tuning_is_rejected():
     eng.close()
 
 
+def test_autotune_with_source_keeps_the_evolution(tmp_path):
+    """With an orbit table long enough for the trials the autotuner times
+    with the source attached; afterwards the state, the iteration count and
+    the source windows are as before: the evolution continues bit for bit
+    as without the autotuner.  The cache key records the source."""
+    grid = STEP_GRIDS[0]
+    phi, pi = W.random_state(grid["nth"], grid["nr"], seed=24)
+    n_orbit = 5 + 624 + 40
+    outs = []
+    for tune in (False, True):
+        eng = gpu_engine(grid)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        gpu_source(eng, grid, dict(SRC, amplitude=50.0), n_orbit)
+        w0 = host(eng.step(5))
+        if tune:
+            cache = tmp_path / "tune_src.txt"
+            table = eng.autotune(str(cache))
+            assert len(table) == 3 + len(BLOCKS)
+            assert "source=1" in cache.read_text()
+            assert eng.info["steps_done"] == 5
+        w1 = host(eng.step(30))
+        outs.append((w0, w1) + tuple(host(x) for x in eng.get_state()))
+        eng.close()
+    assert_bitwise(outs[1], outs[0])
+
+
 def test_autotune_keeps_state_and_serves_cache(tmp_path):
     grid = STEP_GRIDS[0]
     phi, pi = W.random_state(grid["nth"], grid["nr"], seed=23)
