@@ -328,7 +328,7 @@ int teuk_check_finite(teuk_ctx* ctx);
  *             blocks and the remainder as single iterations.
  *   adj_seg_rows  theta rows per wave segment of the adjoint kernel
  *             (teuk_adjoint_step_n), 4, 8 or 16; 0 in teuk_set_tuning leaves
- *             it unchanged.  Default 8 where 8-row segments give more
+ *             it unchanged.  Default 16 where 16-row segments give more
  *             waves than the device has SIMDs, else 4 (teuk_autotune does
  *             not change it).
  * The default (k_steps 1, seg_rows from the grid size) is set by

@@ -148,7 +148,7 @@ __host__ __device__ __forceinline__ int dA_blocks(int win_t) { return (2 * win_t
 // four bodies runs one wave per SIMD.  Parts 1 and 2 together run every wave once, each through
 // the same body as part 0; the source terms only add to dL/dA, so every
 // part gives lambda^n the same bits.
-template <int SEG, int PART>
+template <int SEG, int PART, bool CAPPED>
 __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const ThetaRow* __restrict__ rows) {
     const int lane = threadIdx.x & 63;
     // wave-uniform work item in a scalar register (row branches become scalar
@@ -412,9 +412,11 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
                 P.out_pi[static_cast<size_t>(r3) * ld + i] = oQ;
             }
         }
-        // at 8 rows and more, keep the scheduler from hoisting work across
-        // rows: the live window then fits two waves per SIMD
-        if constexpr (S >= 8) __builtin_amdgcn_sched_barrier(0);
+        // held to two waves per SIMD: keep the scheduler from hoisting work
+        // across rows, so that the live window fits without spills (where
+        // each wave runs alone the barrier only delays the angular-record
+        // loads, so the other launches go without it)
+        if constexpr (CAPPED) __builtin_amdgcn_sched_barrier(0);
     }
     };
 
@@ -457,16 +459,17 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
 
 template <int SEG, int PART>
 __global__ void __launch_bounds__(256) lw_adjoint_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
-    adjoint_iteration<SEG, PART>(P, rows);
+    adjoint_iteration<SEG, PART, false>(P, rows);
 }
 
 // The same iteration held to two waves per SIMD, for the launches without
-// source bodies at segments of 8 and 16 rows (a few registers of the
-// general form may spill; the interior form fits).
+// source bodies at segments of 16 rows, where both forms fit without spills
+// (at 8 rows the general form would spill: those launches run uncapped).
 template <int SEG, int PART>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 lw_adjoint2_kernel(AdjointParams P, const ThetaRow* __restrict__ rows) {
-    adjoint_iteration<SEG, PART>(P, rows);
+    static_assert(SEG == 16, "only the 16-row launches fit two waves per SIMD without spills");
+    adjoint_iteration<SEG, PART, true>(P, rows);
 }
 
 // Sum n per-wave partials into *acc in a fixed order (the result depends only
@@ -524,8 +527,12 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
     return hipGetLastError();
 }
 
+// At 16 rows the kernel with all four bodies does not fit its registers
+// (its arrays go to scratch), so a 16-row reverse iteration with a source is
+// always split; at 4 and 8 rows only where the waves outnumber the SIMDs
+// (where the source-free launch runs more waves per SIMD).
 bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
-    return nstrips * nseg > nsimd && nstrips <= INT16_MAX && nseg <= INT16_MAX;
+    return (seg == 16 || nstrips * nseg > nsimd) && nstrips <= INT16_MAX && nseg <= INT16_MAX;
 }
 
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream, bool source_by_window) {
@@ -559,9 +566,9 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
             break;
         case 8:
             if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
-                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
+                hipLaunchKernelGGL((lw_adjoint_kernel<8, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
             } else if (split) {
-                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
+                hipLaunchKernelGGL((lw_adjoint_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
                 const int sub = P.sub_ns * P.sub_ng;
                 if (sub > 0)
                     hipLaunchKernelGGL((lw_adjoint_kernel<8, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
@@ -569,7 +576,7 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
             } else if (P.fh != nullptr && P.fn != nullptr) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<8, 0>), grid, block, 0, stream, P, P.rows);
             } else {
-                hipLaunchKernelGGL((lw_adjoint2_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
+                hipLaunchKernelGGL((lw_adjoint_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
             }
             break;
         case 16:

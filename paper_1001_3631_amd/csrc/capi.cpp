@@ -315,11 +315,12 @@ int teuk_detail::make_ctx(const teuk_grid_desc* d, const teuk_ws_request* req, v
     }
     // default segment: 8 rows when that still gives at least one wave per
     // SIMD, else 4; the autotuner refines this by measurement.  The adjoint
-    // runs 8-row segments where they give more waves than SIMDs (its
-    // launches then run two waves per SIMD without source bodies), else 4
-    // (each wave alone on its SIMD: shorter segments finish sooner).
+    // runs 16-row segments where they give more waves than SIMDs (its
+    // launches then run two waves per SIMD without source bodies and
+    // without spills), else 4 (each wave alone on its SIMD: shorter
+    // segments finish sooner).
     set_tuning_fields(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) >= c->nsimd) ? 8 : 4, 1);
-    set_adjoint_segment(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 8 + 1) > c->nsimd) ? 8 : 4);
+    set_adjoint_segment(c, (static_cast<long>(c->nstrips) * ((G.nth - 3) / 16 + 1) > c->nsimd) ? 16 : 4);
     const size_t plane_bytes = sizeof(double2) * static_cast<size_t>(c->ld) * G.nth;
     const WsLayout& L = c->lay;
     for (int l = 0; l < 2; ++l)

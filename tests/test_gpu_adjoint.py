@@ -456,14 +456,15 @@ def test_adjoint_fullsize_gradient_vs_central_differences_32_directions():
 
 
 def test_adjoint_segment_setting():
-    """teuk_tuning.adj_seg_rows: default 4 on a small grid and 8 where
-    8-row segments give more waves than SIMDs, 0 keeps the current value,
+    """teuk_tuning.adj_seg_rows: default 4 on a small grid and 16 where
+    16-row segments give more waves than SIMDs, 0 keeps the current value,
     the stepper's own settings do not touch it, invalid values are refused."""
     from paper_1001_3631_amd import _lib as L
-    big = gpu_engine(W.KERR_EMRI["grid"])            # 104 strips x 16 segments of 8 rows
-    assert big.tuning["adj_seg_rows"] == (8 if 104 * 16 > 4 * torch.cuda.get_device_properties(0).multi_processor_count
-                                          else 4)
-    big.close()
+    nsimd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    for grid, waves16 in ((W.KERR_EMRI["grid"], 104 * 8), (W.SCALE_GRID["grid"], 207 * 16)):
+        big = gpu_engine(grid)
+        assert big.tuning["adj_seg_rows"] == (16 if waves16 > nsimd else 4)
+        big.close()
     eng = gpu_engine(STEP_GRIDS[0])
     assert eng.tuning["adj_seg_rows"] == 4
     eng.set_tuning(8, 1, 16)
