@@ -58,6 +58,8 @@ struct teuk_batch {
     teuk::BatchInstance* d_inst = nullptr;
     int4* d_tiles = nullptr;
     int* d_item0 = nullptr;             // per instance: first item (per-iteration mode), + total
+    std::vector<int> h_item0;           // host copy of d_item0
+    std::vector<int> groups;            // per-iteration mode: first instance of each group, + count
     int* d_done = nullptr;
     unsigned long long* d_ticket = nullptr;
     int* d_abort = nullptr;
@@ -145,6 +147,35 @@ int segments(const teuk_ctx* c, int seg) { return (c->G.nth - 3) / seg + 1; }
 // length only changes how each wave walks its strip.  Item offsets of the
 // per-iteration mode: instance k owns items [item0[k], item0[k+1]), one per
 // (strip, segment).
+// Groups of the per-iteration mode.  When the batch's two state levels do
+// not fit the last-level cache (256 MB on MI355X), consecutive instances are
+// grouped so that each group's levels stay within kGroupLevelBytes, and the
+// group is stepped through a whole chunk of iterations before the next: its
+// two levels then stay in the cache over the chunk instead of streaming
+// from HBM every iteration (an instance larger than that is a group of its
+// own).  A batch that fits is one group: splitting it would only shorten
+// its launches.
+constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
+constexpr size_t kGroupLevelBytes = size_t(96) << 20;
+
+void set_batch_groups(teuk_batch* b) {
+    b->groups.clear();
+    size_t total = 0;
+    for (const teuk_ctx* c : b->inst) total += 2 * sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+    const bool split = 2 * total > kLastLevelCacheBytes;
+    size_t acc = 0;
+    for (size_t k = 0; k < b->inst.size(); ++k) {
+        const teuk_ctx* c = b->inst[k];
+        const size_t level = 2 * sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
+        if (k == 0 || (split && acc + level > kGroupLevelBytes)) {
+            b->groups.push_back(static_cast<int>(k));
+            acc = 0;
+        }
+        acc += level;
+    }
+    b->groups.push_back(static_cast<int>(b->inst.size()));
+}
+
 int set_batch_tiles(teuk_batch* b, int seg) {
     std::vector<int4> tiles;
     tiles.reserve(b->max_tiles);
@@ -159,6 +190,7 @@ int set_batch_tiles(teuk_batch* b, int seg) {
         if (items > INT_MAX - 3) return fail(TEUK_EINVAL, "too many work items in one batch");
     }
     item0.push_back(static_cast<int>(items));
+    b->h_item0 = item0;
     HIP_TRY(hipMemcpy(b->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice),
             "batch tiles");
     HIP_TRY(hipMemcpy(b->d_item0, item0.data(), sizeof(int) * item0.size(), hipMemcpyHostToDevice),
@@ -351,6 +383,7 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, const teuk_ws_requ
     b->wall_khz = std::max(khz, 1);
     b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * b->wall_khz);
     const int seg = 16;   // each wave walks a whole strip: long segments, fewest halo rows
+    set_batch_groups(b);
     if (int rc = set_batch_tiles(b, seg)) {
         const std::string msg = teuk_detail::g_last_error;
         free_batch(b);
@@ -446,11 +479,16 @@ int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
         }
         if (b->mode == TEUK_BATCH_PER_ITERATION) {
             if (int rc = upload_instances(b, waveforms, done, src)) return rc;
-            const int ninst = static_cast<int>(b->inst.size());
-            for (int64_t n = 0; n < len; ++n)
-                HIP_TRY(teuk::launch_batch_iteration(b->d_inst, b->d_item0, ninst, b->items, static_cast<int>(n),
-                                                     b->seg_rows, b->stream),
-                        "batch iteration launch");
+            // group by group, each through the whole chunk: one launch per
+            // iteration over the group's instances
+            for (size_t g = 0; g + 1 < b->groups.size(); ++g) {
+                const int k0 = b->groups[g], k1 = b->groups[g + 1];
+                const int base = b->h_item0[k0], items = b->h_item0[k1] - base;
+                for (int64_t n = 0; n < len; ++n)
+                    HIP_TRY(teuk::launch_batch_iteration(b->d_inst + k0, b->d_item0 + k0, k1 - k0, base, items,
+                                                         static_cast<int>(n), b->seg_rows, b->stream),
+                            "batch iteration launch");
+            }
         } else {
             hipGraphExec_t exec = nullptr;
             if (int rc = graph_for(b, len, &exec)) return rc;

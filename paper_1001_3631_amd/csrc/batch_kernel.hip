@@ -208,10 +208,11 @@ hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream) {
 // the launch, so the wave-uniform reads go through the scalar cache.
 template <int SEG>
 __global__ void __launch_bounds__(256) lw_multi_kernel(const BatchInstance* __restrict__ inst,
-                                                       const int* __restrict__ item0, int ninst, int n) {
+                                                       const int* __restrict__ item0, int ninst, int base,
+                                                       int n) {
     const int lane = threadIdx.x & 63;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int item = __builtin_amdgcn_readfirstlane(wg * 4 + (threadIdx.x >> 6));
+    const int item = __builtin_amdgcn_readfirstlane(base + wg * 4 + (threadIdx.x >> 6));
     if (item >= item0[ninst]) return;   // uniform per wave
     // instance: the last k with item0[k] <= item (item0 is non-decreasing)
     int k0 = 0, k1 = ninst - 1;
@@ -276,14 +277,14 @@ __global__ void __launch_bounds__(256) lw_multi_kernel(const BatchInstance* __re
         stream_level<SEG + 2, false, false, kPrefetchRows>(P, A, rn, rh, P.rows);
 }
 
-hipError_t launch_batch_iteration(const BatchInstance* inst, const int* item0, int ninst, int items, int n,
-                                  int seg, hipStream_t stream) {
+hipError_t launch_batch_iteration(const BatchInstance* inst, const int* item0, int ninst, int base, int items,
+                                  int n, int seg, hipStream_t stream) {
     if (items <= 0) return hipSuccess;
     const dim3 grid((items + 3) / 4), block(256);
     switch (seg) {
-        case 4: hipLaunchKernelGGL(lw_multi_kernel<4>, grid, block, 0, stream, inst, item0, ninst, n); break;
-        case 8: hipLaunchKernelGGL(lw_multi_kernel<8>, grid, block, 0, stream, inst, item0, ninst, n); break;
-        case 16: hipLaunchKernelGGL(lw_multi_kernel<16>, grid, block, 0, stream, inst, item0, ninst, n); break;
+        case 4: hipLaunchKernelGGL(lw_multi_kernel<4>, grid, block, 0, stream, inst, item0, ninst, base, n); break;
+        case 8: hipLaunchKernelGGL(lw_multi_kernel<8>, grid, block, 0, stream, inst, item0, ninst, base, n); break;
+        case 16: hipLaunchKernelGGL(lw_multi_kernel<16>, grid, block, 0, stream, inst, item0, ninst, base, n); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -160,10 +160,12 @@ hipError_t launch_block(const StepParams& P, int seg, int k, hipStream_t stream,
                         hipEvent_t ev_stop = nullptr);
 hipError_t launch_batch_reset(const BatchParams& B, hipStream_t stream);
 hipError_t launch_batch(const BatchParams& B, int seg, int waves, hipStream_t stream);
-// One iteration n (counted from the table's cur) of every instance; items =
-// item0[ninst], item0 = per-instance first item at segment length seg.
-hipError_t launch_batch_iteration(const BatchInstance* inst, const int* item0, int ninst, int items, int n,
-                                  int seg, hipStream_t stream);
+// One iteration n (counted from the table's cur) of the ninst instances of
+// inst (a slice of the batch's table); item0 = their first items at segment
+// length seg (slice of the batch's offsets, item0[ninst] its end), base =
+// item0[0], items = item0[ninst] - base.
+hipError_t launch_batch_iteration(const BatchInstance* inst, const int* item0, int ninst, int base, int items,
+                                  int n, int seg, hipStream_t stream);
 hipError_t launch_source_pass(const SourceParams& S, int nbatch, hipStream_t stream);
 hipError_t launch_init_pulse(const PulseParams& Q, hipStream_t stream);
 hipError_t launch_finite(const double2* a, const double2* b, int nr, int nth, int ld, int* flag,
