@@ -538,3 +538,27 @@ def test_large_grid_reverse_sweep_bitwise_across_segments(th_cells):
     for p, q, dA in outs[1:]:
         assert torch.equal(p, outs[0][0]) and torch.equal(q, outs[0][1])
         assert abs(dA - outs[0][2]) <= 1e-13 * abs(outs[0][2]), (dA, outs[0][2])
+
+
+@pytest.mark.parametrize("adj_seg", [4, 8, 16])
+def test_large_grid_reverse_iteration_without_source_against_oracle(adj_seg):
+    """Without a source on 6400 x 128 (more waves than SIMDs at 4 and 8
+    rows: the general-form waves dispatched first), one reverse iteration
+    with the waveform residual against the oracle's, every point."""
+    grid = W.KERR_EMRI["grid"]
+    g = T.Grid(**grid)
+    lp, lq = W.random_state(g.nth, g.nr, seed=81)
+    gw = W.target_noise((3, g.nth), 1.0, seed=82)
+    eng = gpu_engine(grid)
+    eng.set_tuning(8, 1, adj_seg)
+    eng.adjoint_begin(3, to_dev(lp), to_dev(lq), gw=to_dev(gw))
+    eng.adjoint_step(1)
+    p1, q1, _ = eng.adjoint_get(want_dA=False)
+    mp, mq = lp.copy(), lq.copy()
+    mp[:, g.i_ext] += gw[2]
+    rp, rq, _ = T.adjoint_step(g, mp, mq, 2, None)
+    rp[:, g.i_ext] += gw[1]        # the residual of iteration 2, added after the step
+    e = (rel(host(p1), rp), rel(host(q1), rq))
+    print("large grid, no source, adj seg", adj_seg, e)
+    assert max(e) <= 1e-13, e
+    eng.close()
