@@ -108,6 +108,34 @@ def test_block_fullsize_bitwise(cfg):
         assert_bitwise(got, ref)
 
 
+def test_largest_grid_against_oracle():
+    """The largest grid of the workloads (25600 x 512, the HBM-resident one,
+    with its source): two iterations from a seeded random state as single
+    steps at 16 rows and as one blocked (4, 2) launch (what the autotuner
+    picks there) are bitwise equal, and match two oracle iterations at every
+    point and in the waveform."""
+    cfg = W.HBM_PLAIN
+    grid = cfg["grid"]
+    g = T.Grid(**grid)
+    phi, pi = W.random_state(g.nth, g.nr, seed=91)
+    outs = []
+    for tuning in ((16, 1), (4, 2)):
+        eng = gpu_engine(grid)
+        eng.set_tuning(*tuning)
+        gpu_source(eng, grid, cfg["source"], 4)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        w = host(eng.step(2))
+        outs.append((w,) + tuple(host(x) for x in eng.get_state()))
+        eng.close()
+    assert_bitwise(outs[1], outs[0])
+    src = oracle_source(g, cfg["source"], 4)
+    rp, rq, rw = T.evolve(g, phi, pi, 2, src)
+    w, p, q = outs[0]
+    e = (rel(p, rp), rel(q, rq), rel(w, rw))
+    print("25600 x 512, two iterations against the oracle (Phi, Pi, waveform):", e)
+    assert max(e) <= 1e-13, e
+
+
 def test_invalid_tuning_is_rejected():
     from paper_1001_3631_amd._lib import TeukError
     eng = gpu_engine(STEP_GRIDS[0])
