@@ -59,7 +59,8 @@ struct teuk_batch {
     int4* d_tiles = nullptr;
     int* d_item0 = nullptr;             // per instance: first item (per-iteration mode), + total
     std::vector<int> h_item0;           // host copy of d_item0
-    std::vector<int> groups;            // per-iteration mode: first instance of each group, + count
+    std::vector<int> order;             // device table position -> instance (caller's index)
+    std::vector<int> groups;            // per-iteration mode: first table position of each group, + count
     int* d_done = nullptr;
     unsigned long long* d_ticket = nullptr;
     int* d_abort = nullptr;
@@ -148,32 +149,56 @@ int segments(const teuk_ctx* c, int seg) { return (c->G.nth - 3) / seg + 1; }
 // per-iteration mode: instance k owns items [item0[k], item0[k+1]), one per
 // (strip, segment).
 // Groups of the per-iteration mode.  When the batch's two state levels do
-// not fit the last-level cache (256 MB on MI355X), consecutive instances are
-// grouped so that each group's levels stay within kGroupLevelBytes, and the
-// group is stepped through a whole chunk of iterations before the next: its
-// two levels then stay in the cache over the chunk instead of streaming
-// from HBM every iteration (an instance larger than that is a group of its
-// own).  A batch that fits is one group: splitting it would only shorten
+// not fit the last-level cache (256 MB on MI355X), the instances are packed
+// into groups whose levels stay within kGroupLevelBytes (first fit, largest
+// first; an instance larger than that is a group of its own), and each group
+// is stepped through a whole chunk of iterations before the next: its two
+// levels then stay in the cache over the chunk instead of streaming from
+// HBM every iteration.  The device table holds the instances group by group
+// (b->order), so that a group is a contiguous slice of it.  A batch that
+// fits is one group in the caller's order: splitting it would only shorten
 // its launches.
 constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
 constexpr size_t kGroupLevelBytes = size_t(96) << 20;
 
+size_t level_bytes(const teuk_ctx* c) { return 2 * sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth; }
+
 void set_batch_groups(teuk_batch* b) {
-    b->groups.clear();
+    const int n = static_cast<int>(b->inst.size());
+    b->order.resize(n);
+    for (int k = 0; k < n; ++k) b->order[k] = k;
+    b->groups.assign({0, n});
     size_t total = 0;
-    for (const teuk_ctx* c : b->inst) total += 2 * sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
-    const bool split = 2 * total > kLastLevelCacheBytes;
-    size_t acc = 0;
-    for (size_t k = 0; k < b->inst.size(); ++k) {
-        const teuk_ctx* c = b->inst[k];
-        const size_t level = 2 * sizeof(double2) * static_cast<size_t>(c->ld) * c->G.nth;
-        if (k == 0 || (split && acc + level > kGroupLevelBytes)) {
-            b->groups.push_back(static_cast<int>(k));
-            acc = 0;
+    for (const teuk_ctx* c : b->inst) total += level_bytes(c);
+    if (2 * total <= kLastLevelCacheBytes) return;
+    std::vector<int> by_size(b->order);
+    std::stable_sort(by_size.begin(), by_size.end(),
+                     [&](int x, int y) { return level_bytes(b->inst[x]) > level_bytes(b->inst[y]); });
+    std::vector<std::vector<int>> bins;
+    std::vector<size_t> fill;
+    for (int k : by_size) {
+        const size_t sz = level_bytes(b->inst[k]);
+        size_t at = bins.size();
+        for (size_t g = 0; g < bins.size(); ++g)
+            if (fill[g] + sz <= kGroupLevelBytes) {
+                at = g;
+                break;
+            }
+        if (at == bins.size()) {
+            bins.emplace_back();
+            fill.push_back(0);
         }
-        acc += level;
+        bins[at].push_back(k);
+        fill[at] += sz;
     }
-    b->groups.push_back(static_cast<int>(b->inst.size()));
+    b->order.clear();
+    b->groups.clear();
+    for (auto& bin : bins) {
+        std::sort(bin.begin(), bin.end());
+        b->groups.push_back(static_cast<int>(b->order.size()));
+        b->order.insert(b->order.end(), bin.begin(), bin.end());
+    }
+    b->groups.push_back(n);
 }
 
 int set_batch_tiles(teuk_batch* b, int seg) {
@@ -181,8 +206,8 @@ int set_batch_tiles(teuk_batch* b, int seg) {
     tiles.reserve(b->max_tiles);
     std::vector<int> item0;
     long long items = 0;
-    for (size_t k = 0; k < b->inst.size(); ++k) {
-        teuk_ctx* c = b->inst[k];
+    for (size_t k = 0; k < b->inst.size(); ++k) {   // k: position in the device table
+        teuk_ctx* c = b->inst[b->order[k]];
         for (int s = 0; s < c->nstrips; ++s)
             tiles.push_back(make_int4(static_cast<int>(k), s, 0, static_cast<int>(tiles.size())));
         item0.push_back(static_cast<int>(items));
@@ -221,8 +246,9 @@ int upload_instances(teuk_batch* b, void* const* waveforms, int64_t row, const s
     HIP_TRY(hipEventSynchronize(b->h_inst_free[k]), "batch table reuse");
     teuk::BatchInstance* h = b->h_inst[k];
     int tile0 = 0;
-    for (size_t j = 0; j < b->inst.size(); ++j) {
-        const teuk_ctx* c = b->inst[j];
+    for (size_t j = 0; j < b->inst.size(); ++j) {   // j: position in the device table
+        const int k_inst = b->order[j];
+        const teuk_ctx* c = b->inst[k_inst];
         const teuk::Geometry& G = c->G;
         teuk::BatchInstance& I = h[j];
         for (int l = 0; l < 2; ++l)
@@ -244,12 +270,12 @@ int upload_instances(teuk_batch* b, void* const* waveforms, int64_t row, const s
         I.i_ext = G.i_ext;
         I.cur = c->cur;
         I.tile0 = tile0;
-        I.wave = (waveforms && waveforms[j]) ? static_cast<double2*>(waveforms[j]) + row * G.nth : nullptr;
-        I.fh = src[j].fh;
-        I.fn = src[j].fn;
-        I.org = src[j].org;
-        I.win_r = src[j].win_r;
-        I.win_t = src[j].win_t;
+        I.wave = (waveforms && waveforms[k_inst]) ? static_cast<double2*>(waveforms[k_inst]) + row * G.nth : nullptr;
+        I.fh = src[k_inst].fh;
+        I.fn = src[k_inst].fn;
+        I.org = src[k_inst].org;
+        I.win_r = src[k_inst].win_r;
+        I.win_t = src[k_inst].win_t;
         tile0 += I.nstrips;
     }
     HIP_TRY(hipMemcpyAsync(b->d_inst, h, sizeof(teuk::BatchInstance) * b->inst.size(), hipMemcpyHostToDevice,
