@@ -226,10 +226,10 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
     // load used at once, and its wait also waits for every load before it.)
     // The body over output rows [jlo, jhi) at segment length S (the last
     // segment of a column of segments may hold up to S + 2 rows).
-    auto body = [&](auto interior_tag, auto src_tag, auto seg_tag, const int jlo, const int jhi) {
+    auto body = [&](auto interior_tag, auto src_tag, const int jlo, const int jhi) {
     constexpr bool FAST = decltype(interior_tag)::value;
     constexpr bool SRC = decltype(src_tag)::value;
-    constexpr int S = decltype(seg_tag)::value;
+    constexpr int S = SEG;
     // rows jlo-4 .. jhi+5 (jhi - jlo <= S + 2).  Output row r needs mu rows
     // r-2..r+2, whose pole folds can reach two rows further (rows 1, 2 <- row 0).
     constexpr int NT = S + 12;
@@ -428,24 +428,23 @@ __device__ __forceinline__ void adjoint_iteration(const AdjointParams& P, const 
     const bool src = PART != 3 && P.fh != nullptr && P.fn != nullptr && P.win_r > 0 && P.win_t > 0 &&
                      (window_meets(org, false, P.win_r, P.win_t, i0, jlo, jhi - 1) ||
                       window_meets(org, true, P.win_r, P.win_t, i0, jlo, jhi - 1));
-    using SegT = std::integral_constant<int, SEG>;
     if (src) {   // uniform per wave
         if constexpr (PART == 1 || PART == 3) {
             return;
         } else {
             if (interior)
-                body(std::true_type{}, std::true_type{}, SegT{}, jlo, jhi);
+                body(std::true_type{}, std::true_type{}, jlo, jhi);
             else
-                body(std::false_type{}, std::true_type{}, SegT{}, jlo, jhi);
+                body(std::false_type{}, std::true_type{}, jlo, jhi);
         }
     } else {
         if constexpr (PART == 2) {
             return;
         } else {
             if (interior)
-                body(std::true_type{}, std::false_type{}, SegT{}, jlo, jhi);
+                body(std::true_type{}, std::false_type{}, jlo, jhi);
             else
-                body(std::false_type{}, std::false_type{}, SegT{}, jlo, jhi);
+                body(std::false_type{}, std::false_type{}, jlo, jhi);
         }
     }
     // ---- per-wave partial of dL/dA (fixed-order reduction afterwards) ----
