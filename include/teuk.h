@@ -389,7 +389,13 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  *   of a launch boundary.
  * TEUK_BATCH_PER_ITERATION: one launch per iteration covering every
  *   instance, one wave per (instance, strip, theta segment); the launch
- *   boundary orders the iterations.
+ *   boundary orders the iterations.  When the instances' two state levels
+ *   together exceed 256 MiB (the last-level cache), the instances are
+ *   packed into groups of at most 96 MiB per level (first fit, largest
+ *   first; an instance larger than that is a group of its own), and each
+ *   group runs a whole chunk of iterations (up to 256) before the next, one
+ *   launch per iteration over the group, so that its levels stay in the
+ *   cache.  The order of work changes, not the arithmetic.
  * Every point is evaluated by the same device code as teuk_step_n, so an
  * instance's results are bitwise equal to stepping it alone, in both modes.
  *
@@ -413,6 +419,14 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  * teuk_batch_set_mode / get_mode: TEUK_BATCH_PERSISTENT (the default) or
  *   TEUK_BATCH_PER_ITERATION (EINVAL otherwise); applies from the next
  *   teuk_batch_step_n.
+ * teuk_batch_get_groups: the per-iteration mode's groups, fixed at
+ *   teuk_batch_create.  *ngroups: their number (1 when the batch fits the
+ *   cache).  first: NULL or a host array of ngroups + 1 entries, receiving
+ *   the first device-table position of each group and then n.  order: NULL
+ *   or a host array of n entries, receiving the instances (the caller's
+ *   indices k) in device-table order, group by group, ascending within a
+ *   group (the identity when there is one group).  EINVAL for a null
+ *   ngroups.
  * teuk_batch_step_n: nsteps (0 <= nsteps <= INT32_MAX) iterations of every
  *   instance.  waveforms = NULL or a host array of n device pointers, each
  *   NULL or nsteps * nth complex128 (the extraction column after every
@@ -446,6 +460,7 @@ int teuk_batch_set_tuning(teuk_batch* batch, int32_t seg_rows);
 int teuk_batch_get_tuning(const teuk_batch* batch, int32_t* seg_rows);
 int teuk_batch_set_mode(teuk_batch* batch, int32_t mode);
 int teuk_batch_get_mode(const teuk_batch* batch, int32_t* mode);
+int teuk_batch_get_groups(const teuk_batch* batch, int32_t* ngroups, int32_t* first, int32_t* order);
 int teuk_batch_step_n(teuk_batch* batch, int64_t nsteps, void* const* waveforms);
 int teuk_batch_sync(teuk_batch* batch);
 

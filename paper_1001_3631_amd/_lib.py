@@ -137,6 +137,8 @@ SIGNATURES = {
     "teuk_batch_get_tuning": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
     "teuk_batch_set_mode": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "teuk_batch_get_mode": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32)]),
+    "teuk_batch_get_groups": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "teuk_batch_step_n": (ctypes.c_int, [_CTX, ctypes.c_int64, ctypes.POINTER(_P)]),
     "teuk_batch_sync": (ctypes.c_int, [_CTX]),
     "teuk_batch_set_wait_limit": (ctypes.c_int, [_CTX, ctypes.c_double]),

@@ -462,6 +462,18 @@ int teuk_batch_get_mode(const teuk_batch* b, int32_t* mode) {
     return TEUK_OK;
 }
 
+int teuk_batch_get_groups(const teuk_batch* b, int32_t* ngroups, int32_t* first, int32_t* order) {
+    if (int rc = check_batch(b)) return rc;
+    if (ngroups == nullptr) return fail(TEUK_EINVAL, "null output");
+    const int ng = static_cast<int>(b->groups.size()) - 1;
+    *ngroups = ng;
+    if (first != nullptr)
+        for (int g = 0; g <= ng; ++g) first[g] = b->groups[g];
+    if (order != nullptr)
+        for (size_t k = 0; k < b->order.size(); ++k) order[k] = b->order[k];
+    return TEUK_OK;
+}
+
 int teuk_batch_step_n(teuk_batch* b, int64_t nsteps, void* const* waveforms) {
     if (int rc = check_batch(b)) return rc;
     if (nsteps < 0 || nsteps > INT_MAX) return fail(TEUK_EINVAL, "nsteps out of range");

@@ -417,6 +417,17 @@ class Batch:
         """Batch.PERSISTENT or Batch.PER_ITERATION."""
         L.check(self._lib.teuk_batch_set_mode(self.ctx, int(mode)))
 
+    def groups(self):
+        """The per-iteration mode's cache-sized groups, as lists of instance
+        indices in the order they run (one group when the batch fits the
+        last-level cache)."""
+        ng = ctypes.c_int32()
+        L.check(self._lib.teuk_batch_get_groups(self.ctx, ctypes.byref(ng), None, None))
+        first = (ctypes.c_int32 * (ng.value + 1))()
+        order = (ctypes.c_int32 * len(self.instances))()
+        L.check(self._lib.teuk_batch_get_groups(self.ctx, ctypes.byref(ng), first, order))
+        return [list(order[first[g]:first[g + 1]]) for g in range(ng.value)]
+
     def step(self, nsteps, waveform=True, out=None):
         """nsteps iterations of every instance; returns the per-instance
         (nsteps, nth) waveforms (out, if given), or None."""

@@ -222,6 +222,79 @@ def test_batch_with_sources_bitwise_equal_to_single_instances(mode):
         assert np.max(np.abs(got[k][1])) > 0.0
 
 
+# A batch whose two state levels exceed the last-level cache (256 MiB): the
+# per-iteration mode packs its instances into groups of at most 96 MiB per
+# level, first fit, largest first, held group by group in a device table
+# whose order differs from the caller's.
+def _level_bytes(g):
+    return 2 * 16 * ((g["nr"] + 15) // 16 * 16) * g["nth"]
+
+
+def _first_fit_decreasing(sizes, cap):
+    bins, fill = [], []
+    for k in sorted(range(len(sizes)), key=lambda k: -sizes[k]):
+        for b in range(len(bins)):
+            if fill[b] + sizes[k] <= cap:
+                bins[b].append(k)
+                fill[b] += sizes[k]
+                break
+        else:
+            bins.append([k])
+            fill.append(sizes[k])
+    return [sorted(b) for b in bins]
+
+
+def _cache_group_grids():
+    base = dict(W.KERR_EMRI["grid"])
+    return [dict(base, nr=801, nth=33, m=1),        # 0.9 MB per level
+            dict(base, nr=6400, nth=256),           # 52 MB
+            dict(base, nr=6400, nth=384),           # 79 MB
+            dict(base, nr=12800, nth=256),          # 105 MB: beyond a group's 96 MiB, a group of its own
+            dict(base, nr=3200, nth=128, m=3)]      # 13 MB
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
+def test_batch_in_cache_sized_groups_bitwise(mode):
+    """The groups are the first-fit-decreasing packing of the instances'
+    level sizes, and every instance (two with sources, 300 iterations: two
+    source batches) ends bitwise equal to the same instance stepped alone."""
+    grids = _cache_group_grids()
+    sizes = [_level_bytes(g) for g in grids]
+    assert 2 * sum(sizes) > 256 << 20
+    expect = _first_fit_decreasing(sizes, 96 << 20)
+    assert expect == [[3], [0, 2, 4], [1]]
+    nsteps = 300
+    states = [W.random_state(g["nth"], g["nr"], seed=81 + k) for k, g in enumerate(grids)]
+    with_src = (0, 2)
+    b = make_batch(grids)
+    assert b.groups() == expect
+    b.set_mode(mode)
+    for k, (e, (phi, pi)) in enumerate(zip(b.instances, states)):
+        e.set_state(to_dev(phi), to_dev(pi))
+        if k in with_src:
+            gpu_source(e, grids[k], SRC, nsteps)
+    ws = b.step(nsteps)
+    b.sync()
+    got = [(host(w),) + tuple(host(x) for x in e.get_state()) for w, e in zip(ws, b.instances)]
+    b.close()
+    for k, (g, (phi, pi)) in enumerate(zip(grids, states)):
+        eng = gpu_engine(g)
+        eng.set_state(to_dev(phi), to_dev(pi))
+        if k in with_src:
+            gpu_source(eng, g, SRC, nsteps)
+        w = host(eng.step(nsteps))
+        p, q = eng.get_state()
+        eng.close()
+        assert_bitwise(got[k], (w, host(p), host(q)))
+        assert np.max(np.abs(got[k][1])) > 0.0
+
+
+def test_small_batch_is_one_group_in_the_callers_order():
+    b = make_batch(MIXED)
+    assert b.groups() == [list(range(len(MIXED)))]
+    b.close()
+
+
 @pytest.mark.parametrize("mode", MODES, ids=["persistent", "per_iteration"])
 def test_batch_source_instance_against_oracle(mode):
     """An instance with a circular-orbit source, stepped in a batch, against
