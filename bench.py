@@ -78,7 +78,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the 12800 x 256 grid")
+    ap.add_argument("--no-hbm", action="store_true",
+                    help="skip the HBM-resident 25600 x 512 grid and the device-copy ceiling")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-instance workloads")
