@@ -200,14 +200,16 @@ def test_kerr_emri_6400x128_full_run_against_oracle():
 
 def test_adjoint_3200x64_forward_full_run_against_oracle():
     """The gradient workload's forward field: pulse plus circular source,
-    3200 x 64, 20000 iterations, waveform at r* = 400M."""
+    3200 x 64, 20000 iterations, waveform at r* = 400M, in the launch
+    configuration the benchmark uses."""
     from paper_1001_3631_amd.engine import Engine
     main, amp = load("adjoint_3200x64_forward"), load("adjoint_3200x64_forward_amp")
     cfg = W.ADJOINT
     eng = Engine(**cfg["grid"])
+    eng.autotune()                        # the configuration the benchmark times
     eng.init_pulse(**cfg["pulse"])
     _circular(eng, cfg["grid"], cfg["source"], cfg["steps"])
-    run_and_compare("adjoint_3200x64 forward", main, amp, "", *_engine_run(eng))
+    run_and_compare(f"adjoint_3200x64 forward {eng.tuning}", main, amp, "", *_engine_run(eng))
 
 
 @pytest.mark.parametrize("mode", ["persistent", "per_iteration"])
@@ -264,8 +266,10 @@ def test_adjoint_at_scale_first_iterations_against_oracle():
         k, n = run["instance"], run["steps"]
         d = inst[k]
         eng = Engine(**d["grid"])
+        eng.autotune()                    # the configuration the benchmark times
         o = d["orbit"]
         orbit = eng.orbit_eccentric(o["p"], o["e"], 2 * n + 1, M=1.0, a=d["grid"]["a"], chi0=o["chi0"])
         eng.set_source(orbit, src["amplitude"], src["sigma_r_cells"], src["sigma_th_cells"], src["cutoff_sigmas"])
-        run_and_compare(f"adjoint_at_scale instance {k}", sub_meta(main, k), amp, f"i{k}_", *_engine_run(eng))
+        run_and_compare(f"adjoint_at_scale instance {k} {eng.tuning}", sub_meta(main, k), amp, f"i{k}_",
+                        *_engine_run(eng))
         eng.close()
