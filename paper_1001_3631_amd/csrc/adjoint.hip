@@ -526,12 +526,15 @@ hipError_t launch_add_planes(double2* a, double2* b, const double2* ga, const do
     return hipGetLastError();
 }
 
+// The rectangle of source items is held in 16-bit fields.
+bool adjoint_rect_fits(int nstrips, int nseg) { return nstrips <= INT16_MAX && nseg <= INT16_MAX; }
+
 // At 16 rows the kernel with all four bodies does not fit its registers
 // (its arrays go to scratch), so a 16-row reverse iteration with a source is
 // always split; at 4 and 8 rows only where the waves outnumber the SIMDs
 // (where the source-free launch runs more waves per SIMD).
 bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd) {
-    return (seg == 16 || nstrips * nseg > nsimd) && nstrips <= INT16_MAX && nseg <= INT16_MAX;
+    return (seg == 16 || nstrips * nseg > nsimd) && adjoint_rect_fits(nstrips, nseg);
 }
 
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream, bool source_by_window) {
@@ -540,16 +543,23 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
                                                               kAdjHiRows))
                                   : (items + 3) / 4),
         block(256);
-    // With a source on a grid of more waves than SIMDs, the waves without
-    // it run in a launch of their own at two waves per SIMD (seg 4), and the
-    // few with it in a second launch.  Smaller grids run one wave per SIMD
-    // anyway, and the second launch would only add its cost.
-    const bool split = P.fh != nullptr && P.fn != nullptr && adjoint_splits(seg, P.nstrips, P.nseg, nsimd);
+    const bool src = P.fh != nullptr && P.fn != nullptr;
+    // With a source whose windows stay clear of the pole rows, every wave
+    // runs without source terms and dL/dA comes from the windows in the
+    // launch's first blocks (part 3): one launch on any grid, and no wave
+    // waits on window lookups (on 3200 x 64 at seg 4, 12.3 against 12.7 us
+    // for all four bodies in one launch).  Otherwise, on a grid of more waves
+    // than SIMDs, the waves without the source run in a launch of their own
+    // at two waves per SIMD (seg 4), and the few with it in a second launch;
+    // smaller grids run every body in one launch, where the second launch
+    // would only add its cost.
+    const bool by_window = src && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items;
+    const bool split = src && adjoint_splits(seg, P.nstrips, P.nseg, nsimd);
     switch (seg) {
         case 4:
-            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
-                // every wave without its source terms at two waves per SIMD,
-                // and dL/dA from the windows in the launch's first blocks
+            if (by_window) {
+                // every wave without its source terms, and dL/dA from the
+                // windows in the launch's first blocks
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
             } else if (split) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
@@ -557,14 +567,14 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
                 if (sub > 0)
                     hipLaunchKernelGGL((lw_adjoint_kernel<4, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
                                        P.rows);
-            } else if (P.fh != nullptr && P.fn != nullptr) {
+            } else if (src) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 0>), grid, block, 0, stream, P, P.rows);
             } else {
                 hipLaunchKernelGGL((lw_adjoint_kernel<4, 1>), grid, block, 0, stream, P, P.rows);
             }
             break;
         case 8:
-            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
+            if (by_window) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<8, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
             } else if (split) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
@@ -572,14 +582,14 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
                 if (sub > 0)
                     hipLaunchKernelGGL((lw_adjoint_kernel<8, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
                                        P.rows);
-            } else if (P.fh != nullptr && P.fn != nullptr) {
+            } else if (src) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<8, 0>), grid, block, 0, stream, P, P.rows);
             } else {
                 hipLaunchKernelGGL((lw_adjoint_kernel<8, 1>), grid, block, 0, stream, P, P.rows);
             }
             break;
         case 16:
-            if (split && source_by_window && P.dA_part != nullptr && P.win_r <= 64 && 2 * P.win_t <= items) {
+            if (by_window) {
                 hipLaunchKernelGGL((lw_adjoint2_kernel<16, 3>), dim3(grid.x + dA_blocks(P.win_t)), block, 0, stream, P, P.rows);
             } else if (split) {
                 hipLaunchKernelGGL((lw_adjoint2_kernel<16, 1>), grid, block, 0, stream, P, P.rows);
@@ -587,7 +597,7 @@ hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_
                 if (sub > 0)
                     hipLaunchKernelGGL((lw_adjoint_kernel<16, 2>), dim3((sub + 3) / 4), block, 0, stream, P,
                                        P.rows);
-            } else if (P.fh != nullptr && P.fn != nullptr) {
+            } else if (src) {
                 hipLaunchKernelGGL((lw_adjoint_kernel<16, 0>), grid, block, 0, stream, P, P.rows);
             } else {
                 hipLaunchKernelGGL((lw_adjoint2_kernel<16, 1>), grid, block, 0, stream, P, P.rows);

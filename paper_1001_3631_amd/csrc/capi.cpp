@@ -707,7 +707,7 @@ int teuk_adjoint_step_n(teuk_ctx* c, int64_t nsteps, const void* gw) {
             P.fn = c->d_fn + slot * wsz;
             P.org = c->d_org + slot;
             by_window = false;
-            if (teuk::adjoint_splits(c->adj_seg_rows, c->nstrips, c->adj_nseg, c->nsimd)) {
+            if (teuk::adjoint_rect_fits(c->nstrips, c->adj_nseg)) {
                 int s0, ns, g0, ng, r_lo, r_hi;
                 source_items(c, m, c->adj_seg_rows, c->adj_nseg, s0, ns, g0, ng, r_lo, r_hi);
                 P.sub_s0 = static_cast<int16_t>(s0);

@@ -139,13 +139,14 @@ bool valid_segment_rows(int seg);
 // nsimd: SIMDs of the device (a launch of more waves than that splits off
 // the source waves, see adjoint.hip).
 // source_by_window: the windows' rows stay in [3, nth - 4] (no pole folds
-// reach them), so a split launch may run every wave without source terms
-// and take dL/dA from the windows alone.
+// reach them), so the launch may run every wave without source terms and
+// take dL/dA from the windows alone (one launch, on any grid).
 hipError_t launch_adjoint(const AdjointParams& P, int seg, int nsimd, hipStream_t stream,
                           bool source_by_window = false);
-// Whether launch_adjoint runs the waves near the source windows in a launch
-// of their own (then it reads P.sub_*).
-// (the rectangle of source items is held in 16-bit fields, hence the limits)
+// Whether the rectangle of source items fits its 16-bit fields (P.sub_*).
+bool adjoint_rect_fits(int nstrips, int nseg);
+// Whether launch_adjoint, when the windows reach the pole rows, runs the
+// waves near them in a launch of their own (then it reads P.sub_*).
 bool adjoint_splits(int seg, int nstrips, int nseg, int nsimd);
 int reduce_partials_blocks(int n);
 hipError_t launch_reduce_partials(const double* part, int n, double* blk, double* acc, hipStream_t stream);

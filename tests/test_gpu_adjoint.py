@@ -510,6 +510,36 @@ def test_split_reverse_iteration_against_oracle(th_cells, adj_seg):
     assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
 
 
+@pytest.mark.parametrize("adj_seg", [4, 8])
+@pytest.mark.parametrize("th_cells", [None, 2.5, 60.5], ids=["equator", "near_theta0", "near_theta_pi"])
+def test_small_grid_reverse_iteration_against_oracle(th_cells, adj_seg):
+    """On a grid of fewer adjoint waves than SIMDs (3200 x 64: 832 waves at
+    segments of 4) the reverse iteration with a source is one launch: with
+    the windows clear of the poles every wave runs without source terms and
+    dL/dA comes from the windows; with a window that reaches the pole rows
+    every body runs in the one launch.  Against one oracle reverse
+    iteration on the same lambda, whole field and dL/dA."""
+    grid = W.ADJOINT["grid"]
+    g = T.Grid(**grid)
+    n = 8
+    th_p = 0.5 * np.pi if th_cells is None else th_cells * g.hth
+    t = np.arange(2 * n + 1) * 0.5 * g.dt
+    orbit = {"rs": np.full(t.shape, 12.7834), "th": np.full(t.shape, th_p), "phi": 0.0307 * t}
+    eng = gpu_engine(grid)
+    eng.set_tuning(4, 1, adj_seg)
+    eng.set_source(np.stack([orbit["rs"], orbit["th"], orbit["phi"]], axis=1), 1.0, 2.0, 2.0, 8.0)
+    src = T.Source(g, orbit, 1.0, 2.0, 2.0, 8.0)
+    lp, lq = W.random_state(g.nth, g.nr, seed=63)
+    m0 = n - 2
+    eng.adjoint_begin(m0, to_dev(lp), to_dev(lq))
+    eng.adjoint_step(1)
+    p1, q1, dA = eng.adjoint_get()
+    rp, rq, rdA = T.adjoint_step(g, lp, lq, m0 - 1, src)
+    e = (rel(host(p1), rp), rel(host(q1), rq), abs(dA - rdA) / abs(rdA))
+    print("small-grid reverse iteration", th_cells, adj_seg, e)
+    assert e[0] <= 1e-13 and e[1] <= 1e-13 and e[2] <= 1e-12, e
+
+
 @pytest.mark.parametrize("th_cells", [None, 2.5], ids=["equator", "near_theta0"])
 def test_large_grid_reverse_sweep_bitwise_across_segments(th_cells):
     """6400 x 128 with a source: the reverse sweep at adjoint segments of 4,
