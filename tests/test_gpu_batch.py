@@ -290,8 +290,10 @@ def test_batch_in_cache_sized_groups_bitwise(mode):
 
 
 def test_small_batch_is_one_group_in_the_callers_order():
+    from paper_1001_3631_amd import _lib as L
     b = make_batch(MIXED)
     assert b.groups() == [list(range(len(MIXED)))]
+    assert b._lib.teuk_batch_get_groups(b.ctx, None, None, None) == L.TEUK_EINVAL
     b.close()
 
 
