@@ -89,6 +89,33 @@ def test_reverse_sweep_matches_oracle_gradient():
     assert max(e) <= 1e-12, e
 
 
+def test_reverse_steps_compose_and_zero_steps_do_nothing():
+    """A reverse sweep taken as [n], or as [0, 37, 0, n - 37, 0] reverse
+    iterations: the same lambda bit for bit and dL/dA to rounding (reading
+    it mid-sweep sums its partials in other groups); a call of no
+    iterations changes nothing."""
+    grid, n = _adjoint_case(60)
+    g = T.Grid(**grid)
+    lp, lq = W.random_state(g.nth, g.nr, seed=91)
+    gw = to_dev(W.target_noise((n, g.nth), 1.0, seed=92))
+    outs = []
+    for split in ([n], [0, 37, 0, n - 37, 0]):
+        eng = gpu_engine(grid)
+        gpu_source(eng, grid, SRC, n)
+        eng.adjoint_begin(n, to_dev(lp), to_dev(lq), gw=gw)
+        for k in split:
+            before = eng.adjoint_get() if k == 0 else None
+            eng.adjoint_step(k)
+            if before is not None:
+                after = eng.adjoint_get()
+                assert torch.equal(after[0], before[0]) and torch.equal(after[1], before[1])
+                assert after[2] == before[2]
+        outs.append(eng.adjoint_get())
+        eng.close()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert abs(outs[0][2] - outs[1][2]) <= 1e-13 * abs(outs[0][2]), (outs[0][2], outs[1][2])
+
+
 def test_gradient_matches_central_differences_on_gpu():
     grid, n = _adjoint_case()
     g = T.Grid(**grid)

@@ -90,7 +90,7 @@ MODES = [0, 1]   # Batch.PERSISTENT, Batch.PER_ITERATION
 @pytest.mark.parametrize("seg", [4, 8, 16])
 def test_batch_bitwise_equal_to_single_instances(seg, mode):
     states = [W.random_state(g["nth"], g["nr"], seed=31 + k) for k, g in enumerate(MIXED)]
-    plan = [5, 5, 3]            # a cached graph replayed, then a new iteration count
+    plan = [5, 0, 5, 3]         # a cached graph replayed (after a call of no iterations), then a new count
     ref = single_runs(MIXED, states, plan)
     got = batch_runs(MIXED, states, plan, seg=seg, mode=mode)
     for a, b in zip(got, ref):

@@ -196,11 +196,12 @@ def test_step_calls_compose_bitwise():
     grid = STEP_GRIDS[0]
     phi, pi = W.random_state(grid["nth"], grid["nr"], seed=3)
     outs = []
-    for split in ([7], [3, 4], [1, 1, 5]):
+    for split in ([7], [3, 4], [1, 1, 5], [0, 7, 0]):   # zero iterations: no work, an empty waveform
         eng = gpu_engine(grid)
         eng.set_state(to_dev(phi), to_dev(pi))
         gpu_source(eng, grid, SRC, 7)
         ws = [host(eng.step(k)) for k in split]
+        assert [w.shape for w in ws] == [(k, grid["nth"]) for k in split]
         p, q = eng.get_state()
         outs.append((np.concatenate(ws), host(p), host(q)))
         assert eng.info["steps_done"] == 7
