@@ -65,7 +65,7 @@ typedef struct teuk_ctx teuk_ctx;
  *   s, m      spin weight (-2..2) and azimuthal number              (Eq. 1, ansatz)
  *   nr, nth   nodes in r* and theta, both ends included: r*_i = rs_min + i h_r,
  *             h_r = (rs_max - rs_min)/(nr-1); theta_j = j h_th, h_th = pi/(nth-1);
- *             nr >= 5, nth >= 7
+ *             nr >= 5, 7 <= nth <= 65535
  *   cfl       dt = cfl * min(h_r, r(rs_min) h_th); 0 < cfl <= 1
  *   rs_extract extraction radius; the waveform is Phi at the nearest node
  *   ko_eps    strength of the theta fourth-difference dissipation added in the

@@ -74,6 +74,9 @@ std::string build_geometry(double M, double a, int s, int m, int nr, int nth,
     if (!(M > 0.0) || !(std::fabs(a) < M)) return "need M > 0 and |a| < M";
     if (s < -2 || s > 2) return "spin weight s must be in -2..2";
     if (nr < 5 || nth < 7) return "need nr >= 5 and nth >= 7";
+    // the per-row kernels (initial data, finiteness check) launch one block
+    // row per theta row, and a launch has at most 65535 of them
+    if (nth > 65535) return "need nth <= 65535";
     if (!(rs_max > rs_min)) return "need rs_max > rs_min";
     if (!(cfl > 0.0 && cfl <= 1.0)) return "need 0 < cfl <= 1";
     const Horizon h = horizon(M, a);

@@ -39,7 +39,7 @@ def _desc(**kw):
     return L.GridDesc(*[base[k] for k, _ in L.GridDesc._fields_])
 
 
-@pytest.mark.parametrize("bad", [dict(a=1.0), dict(a=-1.2), dict(nr=4), dict(nth=6), dict(cfl=0.0),
+@pytest.mark.parametrize("bad", [dict(a=1.0), dict(a=-1.2), dict(nr=4), dict(nth=6), dict(nth=65536), dict(cfl=0.0),
                                  dict(cfl=1.5), dict(rs_max=-60.0), dict(s=3), dict(ko_eps=-0.1),
                                  dict(ko_eps=2.0), dict(rs_extract=1e4), dict(M=0.0)])
 def test_invalid_descriptor_is_rejected_before_any_device_call(bad):
