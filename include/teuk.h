@@ -416,9 +416,9 @@ int teuk_autotune(teuk_ctx* ctx, const char* cache_path, teuk_tune_entry* table,
  *   teuk_destroy refuses it (EINVAL), teuk_batch_destroy frees it.
  * teuk_batch_set_tuning / get_tuning: theta rows per segment, 4, 8 or 16
  *   (EINVAL otherwise); synchronizes.  The default is 16.
- * teuk_batch_set_mode / get_mode: TEUK_BATCH_PERSISTENT (the default) or
- *   TEUK_BATCH_PER_ITERATION (EINVAL otherwise); applies from the next
- *   teuk_batch_step_n.
+ * teuk_batch_set_mode / get_mode: TEUK_BATCH_PER_ITERATION (the default,
+ *   the faster mode on every batch measured) or TEUK_BATCH_PERSISTENT
+ *   (EINVAL otherwise); applies from the next teuk_batch_step_n.
  * teuk_batch_get_groups: the per-iteration mode's groups, fixed at
  *   teuk_batch_create.  *ngroups: their number (1 when the batch fits the
  *   cache).  first: NULL or a host array of ngroups + 1 entries, receiving

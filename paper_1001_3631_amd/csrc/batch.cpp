@@ -44,7 +44,7 @@ struct teuk_batch {
     hipStream_t stream = nullptr;       // caller's stream: every launch and copy
     hipStream_t cap = nullptr;          // private stream used only to capture graphs
     int seg_rows = 8;
-    int mode = TEUK_BATCH_PERSISTENT;
+    int mode = TEUK_BATCH_PER_ITERATION;   // the faster mode on every batch measured
     int ntiles = 0;                     // tiles per iteration at seg_rows
     int items = 0;                      // (strip, segment) items per iteration at seg_rows
     int max_tiles = 0;                  // at the smallest segment (allocation size)
@@ -408,7 +408,7 @@ int teuk_batch_create(int32_t n, const teuk_grid_desc* descs, const teuk_ws_requ
     b->resident_waves = 8 * std::max(cus, 1);
     b->wall_khz = std::max(khz, 1);
     b->wait_limit = static_cast<long long>(kWaitLimitSeconds * 1e3 * b->wall_khz);
-    const int seg = 16;   // each wave walks a whole strip: long segments, fewest halo rows
+    const int seg = 16;   // long segments, fewest halo rows (the autotuner measures 4, 8 and 16)
     set_batch_groups(b);
     if (int rc = set_batch_tiles(b, seg)) {
         const std::string msg = teuk_detail::g_last_error;

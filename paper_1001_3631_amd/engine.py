@@ -352,8 +352,8 @@ class Engine:
 
 class Batch:
     """Many independent instances stepped together (teuk_batch_*): one
-    persistent graph launch per call, or one launch per iteration covering
-    every instance (mode, see set_mode).
+    launch per iteration covering every instance (the default), or one
+    persistent graph launch per call (mode, see set_mode).
 
     grids: list of dicts with Engine's grid parameters.  instances[k] is an
     Engine view of instance k (set_state, init_pulse, get_state, ...)."""

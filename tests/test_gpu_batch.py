@@ -150,9 +150,10 @@ def test_batch_rejects_bad_arguments():
     b = make_batch(grids)
     with pytest.raises(TeukError):
         b.set_tuning(12)
+    assert b.mode == 1                 # the default: one launch per iteration
     with pytest.raises(TeukError):
         b.set_mode(2)
-    assert b.mode == 0
+    assert b.mode == 1
     e = b.instances[0]
     orbit = e.orbit_circular(10.0, 9, M=1.0, a=grids[0]["a"])      # 4 iterations' worth of samples
     e.set_source(orbit, 1.0, 2.0, 2.0, 8.0)
